@@ -1,0 +1,183 @@
+/*
+ * dpsnn.h — C ABI of the MI355X DPSNN-STDP step library (libdpsnn.so).
+ *
+ * The library simulates, on one GPU, the 1 ms step of a 2-D grid of cortical
+ * columns of Izhikevich neurons with individual axonal delays and
+ * spike-timing-dependent plasticity, as described in Paolucci et al.,
+ * arXiv 1310.8478 (Sec. 2, "Methods").  Each step runs, in order:
+ *   LTP of the incoming synapses of the neurons that fired in the previous
+ *   step (Sec. 2, loop item 2.1); delivery of queued axonal spikes to the
+ *   synapses whose delay matches (items 2.3-2.4), current injection and LTD
+ *   (items 2.5-2.6); the neuron update with the thalamic input and the
+ *   raster (item 2.7); and, every weight_update_period steps, the long-term
+ *   plasticity consolidation (Sec. 3, Table 2, last row).
+ *
+ * Conventions for every entry point:
+ *   - Return 0 (DPSNN_OK) on success, a negative DPSNN_E_* code on failure;
+ *     dpsnn_last_error() then returns a thread-local message.  The library
+ *     never aborts the process.
+ *   - Host pointers belong to the caller and are only read or written during
+ *     the call.  Device memory is owned by the network and released by
+ *     dpsnn_destroy().
+ *   - All device work is enqueued on the stream given at build time; the
+ *     read_* calls synchronise that stream before returning.
+ *   - Neuron ids are global: id = column * neurons_per_column + local, with
+ *     column = cy * grid_x + cx; local ids below round(exc_fraction *
+ *     neurons_per_column) are excitatory (RS), the rest inhibitory (FS).
+ *   - Synapses are addressed canonically by g = id * synapses_per_neuron + j,
+ *     j in [0, synapses_per_neuron), independently of the device layout.
+ *   - Spike stamps: a neuron that crosses threshold while step t (0-based)
+ *     is computed gets stamp t + 1; stamps therefore lie in 1..steps_done.
+ */
+#ifndef DPSNN_H
+#define DPSNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPSNN_OK        0
+#define DPSNN_E_INVAL  (-1)   /* invalid argument or configuration */
+#define DPSNN_E_NOMEM  (-2)   /* a device allocation failed */
+#define DPSNN_E_DEVICE (-3)   /* a HIP runtime call failed */
+#define DPSNN_E_RANGE  (-4)   /* requested steps are not (or no longer) held */
+#define DPSNN_E_BUFSZ  (-5)   /* caller buffer too small; *n_out holds the size needed */
+
+/* Current summation modes (the paper fixes no order or precision for the
+ * sum of currents arriving in one step; Sec. 2, "Projection of synapses"). */
+#define DPSNN_SUM_ORDERED 0u  /* fp32 left fold: thalamic picks, stimulus list,
+                                 then deliveries by (delay, source id, synapse j) */
+#define DPSNN_SUM_ATOMIC  1u  /* fp32, unordered atomics: not bit-reproducible */
+#define DPSNN_SUM_FIXED   2u  /* each term rounded to a multiple of 2^-32, summed
+                                 exactly in int64, the total rounded once to fp32 */
+
+#define DPSNN_CONN_CONFIG 0u  /* own_fraction of exc synapses to the own column,
+                                 the rest uniform over the 12 neighbour columns */
+#define DPSNN_CONN_PAPER  1u  /* 76 % own, 3 % each first, 2 % each second, 1 %
+                                 each third neighbour (Sec. 3, after Table 1) */
+
+/* Network description.  Cited values are the paper's; the others are the
+ * measured workloads' constants. */
+typedef struct dpsnn_config {
+    uint32_t grid_x, grid_y;          /* CFX x CFY columns, periodic (Sec. 2) */
+    uint32_t neurons_per_column;      /* 2 .. 65535 */
+    float    exc_fraction;            /* 0.8 (Sec. 2, neuron model) */
+    uint32_t synapses_per_neuron;     /* M, 1 .. 65535 (Sec. 2, projection) */
+    uint32_t conn_mode;               /* DPSNN_CONN_* */
+    float    own_fraction;            /* used by DPSNN_CONN_CONFIG */
+    uint32_t max_delay;               /* 1 .. 31 ms; exc delays uniform in 1..max */
+    float    w_exc_init, w_inh, w_max;
+    float    a_plus, a_minus, tau_plus, tau_minus;  /* STDP rule (Sec. 2) */
+    uint32_t weight_update_period;    /* steps; 0 disables consolidation */
+    float    wu_bias, sd_decay;       /* w += bias + (P - D); P <- decay*(P - D) */
+    float    thalamic_rate;           /* events per column per ms, [0, 64) */
+    float    thalamic_current;        /* mV per thalamic event */
+    uint64_t seed;                    /* Philox key for connectivity and input */
+    uint32_t sum_mode;                /* DPSNN_SUM_* */
+    uint32_t raster_steps;            /* steps of raster kept on device;
+                                         0 = default (1024); at least max_delay+1 */
+} dpsnn_config;
+
+/* Device, stream and allocator.  alloc/free may be NULL, in which case the
+ * library calls hipMalloc/hipFree.  alloc returns device memory of at least
+ * `bytes` bytes usable on `stream`, or NULL on failure. */
+typedef struct dpsnn_device {
+    int   device;                     /* HIP device ordinal */
+    void *stream;                     /* hipStream_t; NULL = the null stream */
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void  (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
+    void *ctx;
+} dpsnn_device;
+
+typedef struct dpsnn_stats {
+    uint64_t steps;           /* steps simulated */
+    uint64_t spikes;          /* spikes emitted (raster rows) */
+    uint64_t events;          /* synaptic deliveries (one per synapse per arrival) */
+    uint64_t ltp_visits;      /* incoming excitatory synapses walked by LTP */
+    uint64_t consolidations;  /* weight-update passes run */
+    /* per-kernel device time, accumulated only while timing is enabled */
+    double   ms_ltp, ms_deliver, ms_neuron, ms_wupdate;
+    uint64_t n_ltp, n_deliver, n_neuron, n_wupdate;
+} dpsnn_stats;
+
+typedef struct dpsnn_net dpsnn_net;
+
+/* Fill *cfg with the defaults: 2x2 grid, 1250 neurons per column, M = 100,
+ * configuration-mode connectivity, the constants listed in the paper and the
+ * workloads, fixed-point summation. */
+int dpsnn_default_config(dpsnn_config *cfg);
+
+/* Device bytes that dpsnn_build_network would allocate for *cfg, without
+ * allocating.  DPSNN_E_INVAL if *cfg is invalid. */
+int dpsnn_footprint_bytes(const dpsnn_config *cfg, uint64_t *bytes);
+
+/* Generate the network on the device (Sec. 2, "Initial construction of the
+ * connectivity infrastructure" and "Distributed generation of reproducible
+ * connections"): every synapse is drawn from a counter-based generator keyed
+ * by (seed) with counter (id, j), so the network does not depend on launch
+ * shapes.  On success *out owns all device state; the call returns after the
+ * build has completed on the stream. */
+int dpsnn_build_network(const dpsnn_config *cfg, const dpsnn_device *dev, dpsnn_net **out);
+
+/* Enqueue n_steps 1 ms steps (Sec. 2, loop items 2.1-2.7, plus the periodic
+ * consolidation).  Asynchronous on the network's stream. */
+int dpsnn_step(dpsnn_net *net, uint32_t n_steps);
+
+/* Wait for all enqueued work of the network. */
+int dpsnn_sync(dpsnn_net *net);
+
+/* Steps completed so far (the next step index). */
+int dpsnn_time(dpsnn_net *net, uint32_t *t);
+
+/* Spikes with stamp in [t_begin, t_end), sorted by (stamp, id), written to
+ * times[] and ids[] (each of capacity cap).  *n_out receives the number of
+ * spikes.  DPSNN_E_RANGE if the range reaches past the last step or before
+ * the retained raster window; DPSNN_E_BUFSZ if cap is too small. */
+int dpsnn_read_spikes(dpsnn_net *net, uint32_t t_begin, uint32_t t_end,
+                      uint32_t *times, uint32_t *ids, size_t cap, size_t *n_out);
+
+/* Synaptic state of canonical synapses [first, first + count): weight w,
+ * potentiation accumulator P and depression accumulator D (the synaptic
+ * derivative is P - D).  Any output pointer may be NULL. */
+int dpsnn_read_weights(dpsnn_net *net, uint64_t first, uint64_t count,
+                       float *w, float *P, float *D);
+
+/* Connectivity of canonical synapses [first, first + count): global target
+ * id and delay in ms.  Either pointer may be NULL. */
+int dpsnn_read_connectivity(dpsnn_net *net, uint64_t first, uint64_t count,
+                            uint32_t *target, uint8_t *delay);
+
+/* Membrane potential v and recovery variable u of every neuron (Sec. 2,
+ * observables); arrays of length grid_x*grid_y*neurons_per_column. */
+int dpsnn_read_state(dpsnn_net *net, float *v, float *u);
+
+int dpsnn_get_stats(dpsnn_net *net, dpsnn_stats *stats);
+
+/* External stimulus (test hook): entry e adds mv[e] to the input current of
+ * neuron id[e] in step t[e], after the thalamic input.  Replaces any previous
+ * list.  n may be 0 to clear. */
+int dpsnn_set_stimulus(dpsnn_net *net, const uint32_t *t, const uint32_t *id,
+                       const float *mv, size_t n);
+
+/* Per-kernel device timers (Table 2's per-block profiling): when enabled,
+ * every kernel launch of dpsnn_step is bracketed by events and its duration
+ * accumulated into dpsnn_stats at the next dpsnn_get_stats. */
+int dpsnn_set_timing(dpsnn_net *net, int enable);
+
+/* Launch-shape knobs (results never depend on them): key 0 = delivery block
+ * size, 1 = LTP block size, 2 = LDS current window (1 on, 0 off),
+ * 3 = events-per-lane unroll in delivery (1, 2 or 4). */
+int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
+
+void dpsnn_destroy(dpsnn_net *net);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *dpsnn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPSNN_H */

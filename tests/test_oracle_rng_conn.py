@@ -1,0 +1,204 @@
+"""Pins of the oracle's generator, connectivity and thalamic input.
+
+Philox is pinned by published known-answer vectors; connectivity by the exact
+structural rules of Sec. 2 ("Projection of synapses", "Bidimensional arrays of
+neural columns") and by chi-square tests of the uniform draws; the thalamic
+input by its exact count and the uniformity of its picks.
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_1310_8478_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+RING = [(1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (-1, 1), (1, -1), (-1, -1),
+        (2, 0), (-2, 0), (0, 2), (0, -2)]
+
+
+def _kat():
+    out = []
+    for line in open(os.path.join(GOLD, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        lhs, rhs = line.split("->")
+        a = [int(x, 16) for x in lhs.split()]
+        b = tuple(int(x, 16) for x in rhs.split())
+        out.append((tuple(a[:4]), tuple(a[4:]), b))
+    return out
+
+
+@pytest.mark.parametrize("ctr,key,want", _kat())
+def test_philox_known_answers(orc, ctr, key, want):
+    assert orc.philox(ctr, key) == want
+
+
+def _conn(orc, cfg):
+    n = orc.Net(cfg, 1)
+    s = n.synapses()
+    N, M = n.N, n.M
+    n.close()
+    return s, N, M
+
+
+def _col(cfg, k):
+    c = k // cfg["neurons_per_column"]
+    return c % cfg["grid_x"], c // cfg["grid_x"]
+
+
+@pytest.mark.parametrize("grid", [(2, 2), (5, 4), (1, 1)])
+def test_connectivity_structure_exact(orc, grid):
+    cfg = W.make_config(grid_x=grid[0], grid_y=grid[1], neurons_per_column=200,
+                        synapses_per_neuron=60)
+    s, N, M = _conn(orc, cfg)
+    Ncol, GX, GY = 200, grid[0], grid[1]
+    Ne = orc.exc_per_column(cfg)
+    assert Ne == 160
+    Mown = int(np.floor(cfg["own_fraction"] * M + 0.5))
+    ids = np.repeat(np.arange(N), M)
+    j = np.tile(np.arange(M), N)
+    tgt, dly = s["tgt"].astype(np.int64), s["dly"].astype(np.int64)
+    src_l = ids % Ncol
+    exc = src_l < Ne
+    # no self-synapses, targets in range
+    assert (tgt != ids).all() and (tgt < N).all()
+    # inhibitory: own-column excitatory targets, minimum delay, weight w_inh
+    inh = ~exc
+    assert (tgt[inh] // Ncol == ids[inh] // Ncol).all()
+    assert (tgt[inh] % Ncol < Ne).all()
+    assert (dly[inh] == 1).all()
+    assert (s["w"][inh] == np.float32(cfg["w_inh"])).all()
+    # excitatory: delays in 1..Dmax; weight w_exc_init
+    assert ((dly[exc] >= 1) & (dly[exc] <= cfg["max_delay"])).all()
+    assert (s["w"][exc] == np.float32(cfg["w_exc_init"])).all()
+    # own-column quota by synapse index; other synapses land on a ring column
+    sx, sy = (ids // Ncol) % GX, (ids // Ncol) // GX
+    tx, ty = (tgt // Ncol) % GX, (tgt // Ncol) // GX
+    own = exc & (j < Mown)
+    assert ((tx[own] == sx[own]) & (ty[own] == sy[own])).all()
+    nb = exc & (j >= Mown)
+    ok = np.zeros(nb.sum(), dtype=bool)
+    for dx, dy in RING:
+        ok |= (tx[nb] == (sx[nb] + dx) % GX) & (ty[nb] == (sy[nb] + dy) % GY)
+    assert ok.all()
+    # P and D start at zero
+    assert not s["P"].any() and not s["D"].any()
+
+
+def test_single_column_projects_to_itself(orc):
+    # Sec. 2: with a single column all synapses are projected by the column to itself.
+    cfg = W.make_config(grid_x=1, grid_y=1, neurons_per_column=300, synapses_per_neuron=40)
+    s, N, M = _conn(orc, cfg)
+    assert (s["tgt"] < 300).all()
+
+
+@pytest.mark.parametrize("seed", [1311, 1312, 1313, 1314])
+def test_connectivity_statistics(orc, seed):
+    cfg = W.make_config(grid_x=6, grid_y=6, neurons_per_column=250,
+                        synapses_per_neuron=100, seed=seed)
+    s, N, M = _conn(orc, cfg)
+    Ncol, GX, GY = 250, 6, 6
+    Ne = orc.exc_per_column(cfg)
+    ids = np.repeat(np.arange(N), M)
+    j = np.tile(np.arange(M), N)
+    exc = (ids % Ncol) < Ne
+    tgt = s["tgt"].astype(np.int64)
+    # exc delays uniform over 1..20
+    cnt = np.bincount(s["dly"][exc], minlength=21)[1:]
+    assert stats.chisquare(cnt).pvalue > 1e-4
+    # neighbour choice uniform over the 12 ring offsets (6x6: all distinct)
+    nb = exc & (j >= 50)
+    sx, sy = (ids[nb] // Ncol) % GX, (ids[nb] // Ncol) // GX
+    tx, ty = (tgt[nb] // Ncol) % GX, (tgt[nb] // Ncol) // GX
+    slot = np.full(nb.sum(), -1)
+    for q, (dx, dy) in enumerate(RING):
+        slot[(tx == (sx + dx) % GX) & (ty == (sy + dy) % GY)] = q
+    assert (slot >= 0).all()
+    assert stats.chisquare(np.bincount(slot, minlength=12)).pvalue > 1e-4
+    # neighbour targets uniform over the column's neurons
+    assert stats.chisquare(np.bincount(tgt[nb] % Ncol, minlength=Ncol)).pvalue > 1e-4
+    # own-column targets uniform over the column minus the source itself:
+    # the relative offset (target - source) mod Ncol is uniform over 1..Ncol-1
+    own = exc & (j < 50)
+    rel = (tgt[own] % Ncol - ids[own] % Ncol) % Ncol
+    assert (rel != 0).all()
+    assert stats.chisquare(np.bincount(rel, minlength=Ncol)[1:]).pvalue > 1e-4
+    # inhibitory targets uniform over the column's excitatory neurons
+    inh = ~exc
+    assert stats.chisquare(np.bincount(tgt[inh] % Ncol, minlength=Ne)).pvalue > 1e-4
+
+
+def _golden_quotas():
+    out = []
+    for line in open(os.path.join(GOLD, "paper_quotas.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        m, rest = line.split(":")
+        out.append((int(m), [int(x) for x in rest.split()]))
+    return out
+
+
+@pytest.mark.parametrize("M,want", _golden_quotas())
+def test_paper_quotas(orc, M, want):
+    assert orc.paper_blocks(M) == want
+
+
+@pytest.mark.parametrize("M", [1, 7, 13, 99, 250, 333, 1000, 10000])
+def test_paper_quotas_largest_remainder(orc, M):
+    from fractions import Fraction
+    q = [Fraction(76, 100)] + [Fraction(3, 100)] * 4 + [Fraction(2, 100)] * 4 + [Fraction(1, 100)] * 4
+    got = orc.paper_blocks(M)
+    assert sum(got) == M
+    exact = [x * M for x in q]
+    # each count is floor or ceil of its exact share, and the extra units go to
+    # the largest fractional parts
+    for g, e in zip(got, exact):
+        assert g in (int(e), int(e) + 1)
+    fl = [int(e) for e in exact]
+    extra = [i for i in range(13) if got[i] > fl[i]]
+    rest = [i for i in range(13) if got[i] == fl[i]]
+    if extra and rest:
+        assert min(exact[i] - fl[i] for i in extra) >= max(exact[i] - fl[i] for i in rest)
+
+
+def test_paper_mode_blocks(orc):
+    cfg = W.paper_shaped(grid=(6, 6), M=200, neurons_per_column=100)
+    s, N, M = _conn(orc, cfg)
+    Ncol, GX, GY = 100, 6, 6
+    Ne = orc.exc_per_column(cfg)
+    blocks = orc.paper_blocks(200)
+    edges = np.cumsum([0] + blocks)
+    ids = np.repeat(np.arange(N), M)
+    j = np.tile(np.arange(M), N)
+    exc = (ids % Ncol) < Ne
+    tgt = s["tgt"].astype(np.int64)
+    sx, sy = (ids // Ncol) % GX, (ids // Ncol) // GX
+    tx, ty = (tgt // Ncol) % GX, (tgt // Ncol) // GX
+    for slot in range(13):
+        m = exc & (j >= edges[slot]) & (j < edges[slot + 1])
+        dx, dy = (0, 0) if slot == 0 else RING[slot - 1]
+        assert ((tx[m] == (sx[m] + dx) % GX) & (ty[m] == (sy[m] + dy) % GY)).all()
+
+
+def test_thalamic_counts_and_uniformity(orc):
+    cfg = W.make_config(grid_x=3, grid_y=3, neurons_per_column=50, thalamic_rate=1.0)
+    picks = [orc.thalamic(cfg, c, t) for c in range(9) for t in range(2000)]
+    assert all(len(p) == 1 for p in picks)
+    flat = np.array([p[0] for p in picks])
+    assert stats.chisquare(np.bincount(flat, minlength=50)).pvalue > 1e-4
+
+
+@pytest.mark.parametrize("rate", [0.0, 0.5, 1.5, 2.0, 4.25])
+def test_thalamic_fractional_rate(orc, rate):
+    cfg = W.make_config(grid_x=2, grid_y=2, neurons_per_column=40,
+                        thalamic_rate=float(np.float32(rate)))
+    n = np.array([len(orc.thalamic(cfg, c, t)) for c in range(4) for t in range(4000)])
+    whole = int(np.floor(rate))
+    assert set(np.unique(n)) <= {whole, whole + 1}
+    frac = rate - whole
+    # mean within 5 sigma of the Bernoulli(frac) expectation
+    sd = np.sqrt(max(frac * (1 - frac), 1e-12) / len(n))
+    assert abs(n.mean() - rate) <= 5 * sd + 1e-12
