@@ -1,0 +1,196 @@
+"""Benchmark of the DPSNN-STDP 1 ms step on one MI355X.
+
+One bench step is one 1 ms simulation step of the whole hot path: LTP of the
+previous step's spikes, delivery + current injection + LTD, the neuron update
+with thalamic input and raster, and (every 1000th step) the weight
+consolidation.  Inputs are synthetic and seeded (the paper's workloads are
+themselves synthetic); the network is generated on the device before timing
+and is resident in HBM when the timed region starts.
+
+Prints one JSON line: synaptic events/s over the timed steps, plus the
+roofline of the dominant kernel (algorithmic bytes / its average duration,
+measured with HIP events on the library's stream) and the CPU oracle's
+events/s on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per unit of work (state that stays cache-resident --
+# neuron spike history, acc, offsets, tables -- is not counted).
+BYTES_EXC_EVENT_U16 = 2 + 4 + 8     # target index, weight, LTD accumulator read+write
+BYTES_INH_EVENT_U16 = 2             # target index (inhibitory weight is a constant)
+BYTES_LTP_VISIT = 4 + 8             # packed source/delay, P read+write
+BYTES_NEURON = 16 + 16 + 8          # v,u r+w; acc r+w (int64); hist r+w
+BYTES_CONSOLIDATION = 4 + 8 + 8 + 8  # forward index, P, w, D read+write per exc synapse
+
+KERNELS = ("ltp", "deliver", "neuron", "wupdate")
+
+
+def _describe(name, cfg):
+    return (f"{name}: {cfg['grid_x']}x{cfg['grid_y']} columns x {cfg['neurons_per_column']} "
+            f"Izhikevich neurons (80% RS / 20% FS), M={cfg['synapses_per_neuron']} synapses/neuron, "
+            f"delays 1-{cfg['max_delay']} ms, STDP, thalamic {cfg['thalamic_rate']:g}/column/ms")
+
+
+def cpu_baseline(cfg, budget_s: float):
+    """The oracle, as it stands, on a 2x2-column patch of the workload (same
+    column size, M and constants), single-threaded, stepped until about
+    budget_s seconds of CPU work; events per second of oracle stepping."""
+    from oracle import oracle as O
+    patch = dict(cfg)
+    patch["grid_x"], patch["grid_y"] = 2, 2
+    patch["sum_mode"] = 2
+    cap = 5000
+    net = O.Net(patch, cap)
+    steps, elapsed = 0, 0.0
+    chunk = 5
+    while elapsed < budget_s and steps + chunk <= cap:
+        t0 = time.perf_counter()
+        net.run(chunk)
+        elapsed += time.perf_counter() - t0
+        steps += chunk
+    ev = net.counters()["events"]
+    net.close()
+    return {
+        "value": ev / elapsed if elapsed > 0 else None, "unit": "synaptic events/s",
+        "cores": 1, "kind": "oracle",
+        "sample": (f"oracle (plain C, 1 thread) on a 2x2-column patch of the workload, "
+                   f"steps 0..{steps}, {ev} events in {elapsed:.1f} s"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large"])
+    ap.add_argument("--mode", default="fixed", choices=["fixed", "atomic", "ordered"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune", default="", help="key=value,... passed to dpsnn_set_tuning")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU halo exchange is a design only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1310_8478_amd import dpsnn as dp
+    from paper_1310_8478_amd import workloads as W
+
+    mode = {"fixed": W.SUM_FIXED, "atomic": W.SUM_ATOMIC, "ordered": W.SUM_ORDERED}[args.mode]
+    make, _ = W.WORKLOADS[args.workload]
+    cfg = make(sum_mode=mode)
+    torch.cuda.set_device(0)
+
+    t0 = time.perf_counter()
+    net = dp.Network(cfg, device=0)
+    build_s = time.perf_counter() - t0
+    for kv in filter(None, args.tune.split(",")):
+        k, v = kv.split("=")
+        net.set_tuning(int(k), int(v))
+    print(f"[bench] built {args.workload} in {build_s:.2f} s", file=sys.stderr, flush=True)
+
+    done = 0
+    while done < args.warmup:
+        n = min(100, args.warmup - done)
+        net.step(n)
+        net.sync()
+        done += n
+    net.set_timing(True)
+    s0 = net.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.steps:
+        n = min(100, args.steps - done)
+        net.step(n)
+        done += n
+        if done % 500 == 0 or done == args.steps:
+            net.sync()
+            print(f"[bench] {done}/{args.steps} steps", file=sys.stderr, flush=True)
+    net.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s1 = net.stats()
+    net.close()
+
+    d = {k: s1[k] - s0[k] for k in s1 if isinstance(s1[k], (int, float))}
+    N = cfg["grid_x"] * cfg["grid_y"] * cfg["neurons_per_column"]
+    M = cfg["synapses_per_neuron"]
+    events = d["events"]
+    exc_ev = d["events_exc"]
+    inh_ev = events - exc_ev
+    sim_s = args.steps / 1000.0
+    rate_hz = d["spikes"] / N / sim_s
+    tgt16 = 13 * cfg["neurons_per_column"] <= 65536
+    extra = 0 if tgt16 else 2
+    bytes_k = {
+        "deliver": exc_ev * (BYTES_EXC_EVENT_U16 + extra) + inh_ev * (BYTES_INH_EVENT_U16 + extra),
+        "ltp": d["ltp_visits"] * BYTES_LTP_VISIT,
+        "neuron": d["n_neuron"] * N * BYTES_NEURON,
+        "wupdate": d["n_wupdate"] * int(cfg["grid_x"] * cfg["grid_y"] * round(
+            cfg["exc_fraction"] * cfg["neurons_per_column"]) * M) * BYTES_CONSOLIDATION,
+    }
+    kern = {}
+    for k in KERNELS:
+        ms, n = d[f"ms_{k}"], d[f"n_{k}"]
+        if n == 0:
+            continue
+        kern[k] = {"launches": n, "total_ms": round(ms, 3), "avg_us": round(1000 * ms / n, 3),
+                   "algo_bytes_per_launch": bytes_k[k] / n,
+                   "achieved_GBs": round(bytes_k[k] / (ms / 1000.0) / 1e9, 1) if ms > 0 else None}
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    ach = kern[dom]["achieved_GBs"]
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": None,
+            "kernel": f"k_{dom}", "avg_launch_us": kern[dom]["avg_us"],
+            "algo_bytes_per_launch": kern[dom]["algo_bytes_per_launch"]}
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg, args.cpu_seconds)
+    out = {
+        "metric": "synaptic events/s",
+        "value": events / wall,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if mode != W.SUM_FIXED else "f32+i64acc",
+        "data": "synthetic (seeded Philox network and thalamic input, as in the paper)",
+        "config": {
+            "workload": _describe(args.workload, cfg),
+            "neurons": N, "synapses": N * M, "sum_mode": args.mode,
+            "timed_steps": f"{args.warmup}..{args.warmup + args.steps - 1}",
+        },
+        "wall_s_per_sim_s_per_hz": (wall / sim_s) / rate_hz if rate_hz > 0 else None,
+        "wall_s_per_sim_s": wall / sim_s,
+        "rate_hz": rate_hz,
+        "build_s": build_s,
+        "kernels": kern,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

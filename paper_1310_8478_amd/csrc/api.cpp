@@ -1,0 +1,684 @@
+// C ABI of libdpsnn: configuration checks, device memory, the build and step
+// sequencing, and read-back.  Every device computation runs in the HIP
+// kernels of build.hip, step.hip and read.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "net.h"
+
+using namespace dpsnn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define DPSNN_HIP(expr)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(DPSNN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Derived {
+    uint32_t N, C, Ncol, Ne, M, Dmax, W, R, M_own;
+    uint64_t S, S_exc;
+    bool tgt16;
+};
+
+bool finite_in(float x, float lo, float hi) { return std::isfinite(x) && x >= lo && x <= hi; }
+
+int validate(const dpsnn_config* c, Derived* o) {
+    if (!c) return fail(DPSNN_E_INVAL, "config is NULL");
+    if (c->grid_x < 1 || c->grid_y < 1 || c->grid_x > 65535 || c->grid_y > 65535)
+        return fail(DPSNN_E_INVAL, "grid_x and grid_y must be in 1..65535");
+    if (c->neurons_per_column < 2 || c->neurons_per_column > 65535)
+        return fail(DPSNN_E_INVAL, "neurons_per_column must be in 2..65535");
+    if (!finite_in(c->exc_fraction, 0.0f, 1.0f)) return fail(DPSNN_E_INVAL, "exc_fraction must be in [0, 1]");
+    const uint32_t Ncol = c->neurons_per_column;
+    const uint32_t Ne = (uint32_t)std::floor((double)c->exc_fraction * (double)Ncol + 0.5);
+    if (Ne < 1 || Ne > Ncol) return fail(DPSNN_E_INVAL, "a column needs at least one excitatory neuron");
+    if (c->synapses_per_neuron < 1 || c->synapses_per_neuron > 65535)
+        return fail(DPSNN_E_INVAL, "synapses_per_neuron must be in 1..65535");
+    if (c->max_delay < 1 || c->max_delay > 31) return fail(DPSNN_E_INVAL, "max_delay must be in 1..31");
+    if (c->conn_mode > 1u) return fail(DPSNN_E_INVAL, "conn_mode must be 0 or 1");
+    if (c->conn_mode == 0u && !finite_in(c->own_fraction, 0.0f, 1.0f))
+        return fail(DPSNN_E_INVAL, "own_fraction must be in [0, 1]");
+    const uint64_t C = (uint64_t)c->grid_x * c->grid_y;
+    const uint64_t N = C * Ncol;
+    if (N >= (1ull << 26)) return fail(DPSNN_E_INVAL, "at most 2^26 - 1 neurons per network");
+    const uint64_t S = N * c->synapses_per_neuron;
+    if (S >= (1ull << 32)) return fail(DPSNN_E_INVAL, "at most 2^32 - 1 synapses per network");
+    if (!finite_in(c->w_exc_init, -1000.f, 1000.f) || !finite_in(c->w_inh, -1000.f, 1000.f) ||
+        !finite_in(c->w_max, 0.f, 1000.f))
+        return fail(DPSNN_E_INVAL, "weights must be finite, |w| <= 1000, w_max >= 0");
+    if (!finite_in(c->a_plus, 0.f, 1000.f) || !finite_in(c->a_minus, 0.f, 1000.f))
+        return fail(DPSNN_E_INVAL, "STDP amplitudes must be finite and >= 0");
+    if (!finite_in(c->tau_plus, 1e-3f, 1000.f) || !finite_in(c->tau_minus, 1e-3f, 1000.f))
+        return fail(DPSNN_E_INVAL, "STDP time constants must be in [1e-3, 1000] ms");
+    if (!finite_in(c->wu_bias, -1000.f, 1000.f) || !finite_in(c->sd_decay, -1000.f, 1000.f))
+        return fail(DPSNN_E_INVAL, "consolidation constants must be finite");
+    if (!(std::isfinite(c->thalamic_rate) && c->thalamic_rate >= 0.f && c->thalamic_rate < 64.f))
+        return fail(DPSNN_E_INVAL, "thalamic_rate must be in [0, 64)");
+    if (!finite_in(c->thalamic_current, -1000.f, 1000.f))
+        return fail(DPSNN_E_INVAL, "thalamic_current must be finite, |x| <= 1000");
+    if (c->sum_mode > 2u) return fail(DPSNN_E_INVAL, "sum_mode must be 0, 1 or 2");
+    uint32_t R = c->raster_steps ? c->raster_steps : 1024u;
+    if (R < c->max_delay + 1u) return fail(DPSNN_E_INVAL, "raster_steps must be at least max_delay + 1");
+    if (R > (1u << 20)) return fail(DPSNN_E_INVAL, "raster_steps must be at most 2^20");
+    o->N = (uint32_t)N;
+    o->C = (uint32_t)C;
+    o->Ncol = Ncol;
+    o->Ne = Ne;
+    o->M = c->synapses_per_neuron;
+    o->Dmax = c->max_delay;
+    o->W = (Ncol + 63) / 64;
+    o->R = R;
+    o->M_own = (uint32_t)std::floor((double)c->own_fraction * (double)o->M + 0.5);
+    if (o->M_own > o->M) o->M_own = o->M;
+    o->S = S;
+    o->S_exc = (uint64_t)C * Ne * o->M;
+    o->tgt16 = (uint64_t)kSlots * Ncol <= 65536ull;
+    return DPSNN_OK;
+}
+
+// Byte sizes of every device array, in allocation order.
+std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
+    const size_t N = d.N, S = d.S, Se = d.S_exc;
+    std::vector<size_t> b = {
+        sizeof(uint32_t) * d.C * kSlots,                  // colmap
+        sizeof(uint32_t) * d.C * kSlots,                  // srcmap
+        sizeof(uint32_t) * ((size_t)d.C * d.Dmax * d.Ncol + 1),  // seg_off
+        (d.tgt16 ? 2 : 4) * S,                            // tgt
+        sizeof(float) * S,                                // w
+        sizeof(float) * S,                                // D
+        sizeof(uint32_t) * (N + 1),                       // rowptr
+        sizeof(uint32_t) * N,                             // cursor
+        sizeof(uint32_t) * Se,                            // rev_srcd
+        sizeof(uint32_t) * Se,                            // rev_fwd
+        sizeof(float) * Se,                               // P
+        sizeof(float) * N, sizeof(float) * N,             // v, u
+        (c->sum_mode == DPSNN_SUM_FIXED ? 8 : 4) * N,     // acc
+        sizeof(uint32_t) * N, sizeof(int32_t) * N, sizeof(int32_t) * N,  // hist, t_old, t_last
+        sizeof(uint64_t) * (size_t)d.R * d.C * d.W,       // ring
+        sizeof(DevStats) * 64,                            // stats
+        sizeof(uint32_t) * (N / 1024 + 2),                // scan_tmp
+    };
+    if (c->sum_mode == DPSNN_SUM_ORDERED) {
+        b.push_back(sizeof(uint32_t) * N);                // ev_cnt
+        b.push_back(sizeof(uint32_t) * (N + 1));          // ev_start
+        b.push_back(sizeof(unsigned long long) * S);      // ev_key
+        b.push_back(sizeof(float) * S);                   // ev_w
+    }
+    return b;
+}
+
+void* dalloc(Net& n, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    void* p = nullptr;
+    if (n.dev.alloc) {
+        p = n.dev.alloc(bytes, n.dev.stream, n.dev.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p) n.allocs.push_back({p, bytes});
+    return p;
+}
+
+void dfree(Net& n, void* p, size_t bytes) {
+    if (!p) return;
+    if (n.dev.free) n.dev.free(p, bytes, n.dev.stream, n.dev.ctx);
+    else (void)hipFree(p);
+}
+
+void release(Net* n) {
+    if (!n) return;
+    (void)hipSetDevice(n->dev.device);
+    (void)hipStreamSynchronize(n->stream);
+    for (auto& a : n->allocs) dfree(*n, a.p, a.bytes);
+    n->allocs.clear();
+    for (auto& tt : n->timed) {
+        (void)hipEventDestroy(tt.a);
+        (void)hipEventDestroy(tt.b);
+    }
+    for (auto e : n->event_pool) (void)hipEventDestroy(e);
+    delete n;
+}
+
+// STDP amplitudes A exp(-dt / tau) for dt = 0, 1, ...: evaluated in fp64,
+// rounded once to fp32, values below FLT_MIN flushed to 0; the table ends
+// where the amplitude becomes 0 (it decreases monotonically).
+std::vector<float> amplitude_table(float A, float tau) {
+    std::vector<float> out;
+    for (uint32_t k = 0; k < (1u << 20); ++k) {
+        const double x = (double)A * std::exp(-(double)k / (double)tau);
+        float f = (float)x;
+        if (std::fabs(f) < FLT_MIN) f = 0.0f;
+        if (f == 0.0f) break;
+        out.push_back(f);
+    }
+    return out;
+}
+
+// Largest-remainder split of M synapses over own column and the 12 neighbour
+// slots with shares 7600/300x4/200x4/100x4 per 10000 (ties to the lower slot).
+void paper_split(uint32_t M, uint32_t end[kSlots]) {
+    static const uint32_t share[kSlots] = {7600, 300, 300, 300, 300, 200, 200, 200, 200,
+                                           100, 100, 100, 100};
+    uint32_t cnt[kSlots];
+    uint64_t rem[kSlots];
+    uint32_t total = 0;
+    for (int s = 0; s < kSlots; ++s) {
+        const uint64_t p = (uint64_t)share[s] * M;
+        cnt[s] = (uint32_t)(p / 10000);
+        rem[s] = p % 10000;
+        total += cnt[s];
+    }
+    while (total < M) {
+        int best = 0;
+        for (int s = 1; s < kSlots; ++s)
+            if (rem[s] > rem[best]) best = s;
+        cnt[best]++;
+        rem[best] = 0;
+        total++;
+    }
+    uint32_t acc = 0;
+    for (int s = 0; s < kSlots; ++s) {
+        acc += cnt[s];
+        end[s] = acc;
+    }
+}
+
+const int kRingDx[12] = {1, -1, 0, 0, 1, -1, 1, -1, 2, -2, 0, 0};
+const int kRingDy[12] = {0, 0, 1, -1, 1, 1, -1, -1, 0, 0, 2, -2};
+
+int wrapi(int x, int n) {
+    const int r = x % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename T>
+int upload(Net& n, T* dst, const std::vector<T>& src) {
+    if (src.empty()) return DPSNN_OK;
+    DPSNN_HIP(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, n.stream));
+    return DPSNN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dpsnn_last_error(void) { return g_err.c_str(); }
+
+int dpsnn_default_config(dpsnn_config* c) {
+    if (!c) return fail(DPSNN_E_INVAL, "config is NULL");
+    std::memset(c, 0, sizeof(*c));
+    c->grid_x = 2;
+    c->grid_y = 2;
+    c->neurons_per_column = 1250;
+    c->exc_fraction = 0.8f;
+    c->synapses_per_neuron = 100;
+    c->conn_mode = DPSNN_CONN_CONFIG;
+    c->own_fraction = 0.5f;
+    c->max_delay = 20;
+    c->w_exc_init = 6.0f;
+    c->w_inh = -5.0f;
+    c->w_max = 10.0f;
+    c->a_plus = 0.1f;
+    c->a_minus = 0.12f;
+    c->tau_plus = 20.0f;
+    c->tau_minus = 20.0f;
+    c->weight_update_period = 1000;
+    c->wu_bias = 0.01f;
+    c->sd_decay = 0.9f;
+    c->thalamic_rate = 1.0f;
+    c->thalamic_current = 20.0f;
+    c->seed = 1310;
+    c->sum_mode = DPSNN_SUM_FIXED;
+    c->raster_steps = 0;
+    return DPSNN_OK;
+}
+
+int dpsnn_footprint_bytes(const dpsnn_config* cfg, uint64_t* bytes) {
+    Derived d;
+    int rc = validate(cfg, &d);
+    if (rc) return rc;
+    if (!bytes) return fail(DPSNN_E_INVAL, "bytes is NULL");
+    uint64_t tot = 0;
+    for (size_t b : array_bytes(cfg, d)) tot += std::max<size_t>(b, 256);
+    // tables (at most a few hundred KB)
+    tot += 2 * 4 * 65536;
+    *bytes = tot;
+    return DPSNN_OK;
+}
+
+int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_net** out) {
+    if (!out) return fail(DPSNN_E_INVAL, "out is NULL");
+    *out = nullptr;
+    Derived dv;
+    int rc = validate(cfg, &dv);
+    if (rc) return rc;
+    if (!dev) return fail(DPSNN_E_INVAL, "device is NULL");
+    if ((dev->alloc == nullptr) != (dev->free == nullptr))
+        return fail(DPSNN_E_INVAL, "alloc and free callbacks must be given together");
+    int ndev = 0;
+    DPSNN_HIP(hipGetDeviceCount(&ndev));
+    if (dev->device < 0 || dev->device >= ndev) return fail(DPSNN_E_INVAL, "no such HIP device");
+    DPSNN_HIP(hipSetDevice(dev->device));
+
+    Net* n = new Net();
+    n->cfg = *cfg;
+    if (n->cfg.raster_steps == 0) n->cfg.raster_steps = dv.R;
+    n->dev = *dev;
+    n->stream = (hipStream_t)dev->stream;
+    n->S = dv.S;
+    n->S_exc = dv.S_exc;
+    n->tgt16 = dv.tgt16;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev->device) == hipSuccess &&
+        lds > 0)
+        n->max_lds = (size_t)lds;
+
+    Dims& d = n->d;
+    std::memset(&d, 0, sizeof(d));
+    d.N = dv.N; d.C = dv.C; d.Ncol = dv.Ncol; d.Ne = dv.Ne; d.M = dv.M; d.Dmax = dv.Dmax;
+    d.GX = cfg->grid_x; d.GY = cfg->grid_y; d.W = dv.W; d.R = dv.R;
+    d.conn_mode = cfg->conn_mode; d.M_own = dv.M_own;
+    paper_split(dv.M, d.paper_end);
+    d.key0 = (uint32_t)(cfg->seed & 0xFFFFFFFFu);
+    d.key1 = (uint32_t)(cfg->seed >> 32);
+    d.w_exc = cfg->w_exc_init; d.w_inh = cfg->w_inh;
+    d.segs = dv.Dmax * dv.Ncol;
+    d.ncol_magic = (uint32_t)(((1ull << 32) + dv.Ncol - 1) / dv.Ncol);
+    const double r = (double)cfg->thalamic_rate;
+    const double fl = std::floor(r);
+    n->thal_whole = (uint32_t)fl;
+    n->thal_thr = (uint32_t)((r - fl) * 4294967296.0);
+    // the LTP block covers one raster word per thread
+    n->ltp_block = std::max<uint32_t>(n->ltp_block, ((dv.W + 63) / 64) * 64);
+
+    const std::vector<size_t> sz = array_bytes(cfg, dv);
+    std::vector<void*> p(sz.size(), nullptr);
+    for (size_t k = 0; k < sz.size(); ++k) {
+        p[k] = dalloc(*n, sz[k]);
+        if (!p[k]) {
+            release(n);
+            return fail(DPSNN_E_NOMEM, "device allocation of " + std::to_string(sz[k]) + " bytes failed");
+        }
+    }
+    size_t k = 0;
+    n->colmap = (uint32_t*)p[k++]; n->srcmap = (uint32_t*)p[k++]; n->seg_off = (uint32_t*)p[k++];
+    n->tgt = p[k++]; n->w = (float*)p[k++]; n->Dacc = (float*)p[k++];
+    n->rowptr = (uint32_t*)p[k++]; n->cursor = (uint32_t*)p[k++];
+    n->rev_srcd = (uint32_t*)p[k++]; n->rev_fwd = (uint32_t*)p[k++]; n->Pacc = (float*)p[k++];
+    n->v = (float*)p[k++]; n->u = (float*)p[k++]; n->acc = p[k++];
+    n->hist = (uint32_t*)p[k++]; n->t_old = (int32_t*)p[k++]; n->t_last = (int32_t*)p[k++];
+    n->ring = (uint64_t*)p[k++]; n->stats = (DevStats*)p[k++]; n->scan_tmp = (uint32_t*)p[k++];
+    if (cfg->sum_mode == DPSNN_SUM_ORDERED) {
+        n->ev_cnt = (uint32_t*)p[k++]; n->ev_start = (uint32_t*)p[k++];
+        n->ev_key = (unsigned long long*)p[k++]; n->ev_w = (float*)p[k++];
+    }
+
+    // column maps
+    std::vector<uint32_t> colmap((size_t)dv.C * kSlots), srcmap((size_t)dv.C * kSlots);
+    for (uint32_t c = 0; c < dv.C; ++c) {
+        const int cx = (int)(c % cfg->grid_x), cy = (int)(c / cfg->grid_x);
+        colmap[(size_t)c * kSlots] = c;
+        srcmap[(size_t)c * kSlots] = c;
+        for (int q = 1; q < kSlots; ++q) {
+            const int gx = (int)cfg->grid_x, gy = (int)cfg->grid_y;
+            colmap[(size_t)c * kSlots + q] =
+                (uint32_t)(wrapi(cy + kRingDy[q - 1], gy) * gx + wrapi(cx + kRingDx[q - 1], gx));
+            srcmap[(size_t)c * kSlots + q] =
+                (uint32_t)(wrapi(cy - kRingDy[q - 1], gy) * gx + wrapi(cx - kRingDx[q - 1], gx));
+        }
+    }
+    std::vector<float> tp = amplitude_table(cfg->a_plus, cfg->tau_plus);
+    std::vector<float> tm = amplitude_table(cfg->a_minus, cfg->tau_minus);
+    n->tp_len = (uint32_t)tp.size();
+    n->tm_len = (uint32_t)tm.size();
+    n->tp = (float*)dalloc(*n, sizeof(float) * std::max<size_t>(tp.size(), 1));
+    n->tm = (float*)dalloc(*n, sizeof(float) * std::max<size_t>(tm.size(), 1));
+    if (!n->tp || !n->tm) {
+        release(n);
+        return fail(DPSNN_E_NOMEM, "device allocation of STDP tables failed");
+    }
+#define DPSNN_TRY(expr)             \
+    do {                            \
+        int rc_ = (expr);           \
+        if (rc_) {                  \
+            release(n);             \
+            return rc_;             \
+        }                           \
+    } while (0)
+#define DPSNN_TRY_HIP(expr)                                                                   \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            release(n);                                                                       \
+            return fail(DPSNN_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+        }                                                                                     \
+    } while (0)
+    DPSNN_TRY(upload(*n, n->colmap, colmap));
+    DPSNN_TRY(upload(*n, n->srcmap, srcmap));
+    DPSNN_TRY(upload(*n, n->tp, tp));
+    DPSNN_TRY(upload(*n, n->tm, tm));
+    const size_t accb = (cfg->sum_mode == DPSNN_SUM_FIXED ? 8 : 4) * (size_t)dv.N;
+    DPSNN_TRY_HIP(hipMemsetAsync(n->Dacc, 0, sizeof(float) * dv.S, n->stream));
+    DPSNN_TRY_HIP(hipMemsetAsync(n->Pacc, 0, sizeof(float) * std::max<uint64_t>(dv.S_exc, 1), n->stream));
+    DPSNN_TRY_HIP(hipMemsetAsync(n->acc, 0, accb, n->stream));
+    DPSNN_TRY_HIP(hipMemsetAsync(n->ring, 0, sizeof(uint64_t) * (size_t)dv.R * dv.C * dv.W, n->stream));
+    DPSNN_TRY_HIP(hipMemsetAsync(n->stats, 0, sizeof(DevStats) * 64, n->stream));
+    if (n->ev_cnt) {
+        DPSNN_TRY_HIP(hipMemsetAsync(n->ev_cnt, 0, sizeof(uint32_t) * dv.N, n->stream));
+        DPSNN_TRY_HIP(hipMemsetAsync(n->ev_start, 0, sizeof(uint32_t) * (dv.N + 1), n->stream));
+    }
+    DPSNN_TRY_HIP(launch_build(*n));
+    // the reverse index must hold exactly the excitatory synapses
+    uint32_t total = 0;
+    DPSNN_TRY_HIP(hipMemcpyAsync(&total, n->rowptr + dv.N, sizeof(uint32_t), hipMemcpyDeviceToHost, n->stream));
+    DPSNN_TRY_HIP(hipMemsetAsync(n->cursor, 0, sizeof(uint32_t) * dv.N, n->stream));
+    DPSNN_TRY_HIP(hipStreamSynchronize(n->stream));
+    if ((uint64_t)total != dv.S_exc) {
+        release(n);
+        return fail(DPSNN_E_DEVICE, "reverse index size mismatch after build");
+    }
+#undef DPSNN_TRY
+#undef DPSNN_TRY_HIP
+    *out = reinterpret_cast<dpsnn_net*>(n);
+    return DPSNN_OK;
+}
+
+int dpsnn_step(dpsnn_net* h, uint32_t n_steps) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    if ((uint64_t)n->t + n_steps >= (1ull << 31)) return fail(DPSNN_E_RANGE, "step count overflow");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    for (uint32_t s = 0; s < n_steps; ++s) {
+        const uint32_t t = n->t;
+        uint32_t sb = 0, se = 0;
+        if (n->stim_n) {
+            auto lo = std::lower_bound(n->stim_t_host.begin(), n->stim_t_host.end(), t);
+            auto hi = std::upper_bound(lo, n->stim_t_host.end(), t);
+            sb = (uint32_t)(lo - n->stim_t_host.begin());
+            se = (uint32_t)(hi - n->stim_t_host.begin());
+        }
+        DPSNN_HIP(launch_step(*n, t, sb, se));
+        n->t = t + 1;
+    }
+    return DPSNN_OK;
+}
+
+int dpsnn_sync(dpsnn_net* h) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    DPSNN_HIP(hipStreamSynchronize(n->stream));
+    return DPSNN_OK;
+}
+
+int dpsnn_time(dpsnn_net* h, uint32_t* t) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n || !t) return fail(DPSNN_E_INVAL, "NULL argument");
+    *t = n->t;
+    return DPSNN_OK;
+}
+
+int dpsnn_read_spikes(dpsnn_net* h, uint32_t t_begin, uint32_t t_end, uint32_t* times,
+                      uint32_t* ids, size_t cap, size_t* n_out) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n || !n_out) return fail(DPSNN_E_INVAL, "NULL argument");
+    *n_out = 0;
+    if (t_end < t_begin) return fail(DPSNN_E_INVAL, "t_end < t_begin");
+    if (t_begin < 1) t_begin = 1;
+    if (t_end <= t_begin) return DPSNN_OK;
+    const uint32_t now = n->t;  // latest stamp
+    if (t_end > now + 1) return fail(DPSNN_E_RANGE, "range reaches past the last simulated step");
+    const Dims& d = n->d;
+    if (now >= d.R && t_begin < now - d.R + 1)
+        return fail(DPSNN_E_RANGE, "range starts before the retained raster window");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    DPSNN_HIP(hipStreamSynchronize(n->stream));
+    const size_t words = (size_t)d.C * d.W;
+    std::vector<uint64_t> buf(words * (t_end - t_begin));
+    for (uint32_t s = t_begin; s < t_end; ++s) {
+        DPSNN_HIP(hipMemcpy(buf.data() + (size_t)(s - t_begin) * words,
+                            n->ring + (size_t)(s % d.R) * words, words * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost));
+    }
+    size_t count = 0;
+    for (uint64_t x : buf) count += (size_t)__builtin_popcountll(x);
+    *n_out = count;
+    if (count > cap) return fail(DPSNN_E_BUFSZ, "spike buffer too small");
+    if (count && (!times || !ids)) return fail(DPSNN_E_INVAL, "NULL output buffer");
+    size_t o = 0;
+    for (uint32_t s = t_begin; s < t_end; ++s) {
+        const uint64_t* row = buf.data() + (size_t)(s - t_begin) * words;
+        for (uint32_t c = 0; c < d.C; ++c) {
+            for (uint32_t w = 0; w < d.W; ++w) {
+                uint64_t m = row[(size_t)c * d.W + w];
+                while (m) {
+                    const uint32_t b = (uint32_t)__builtin_ctzll(m);
+                    m &= m - 1;
+                    times[o] = s;
+                    ids[o] = c * d.Ncol + w * 64 + b;
+                    ++o;
+                }
+            }
+        }
+    }
+    return DPSNN_OK;
+}
+
+static int read_rows_common(Net* n, uint64_t first, uint64_t count, uint32_t* tgt, uint8_t* dly,
+                            float* w, float* P, float* D) {
+    if (first > n->S || count > n->S - first) return fail(DPSNN_E_RANGE, "synapse range out of bounds");
+    if (count == 0) return DPSNN_OK;
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    const uint32_t M = n->d.M;
+    const uint32_t i0 = (uint32_t)(first / M);
+    const uint32_t i1 = (uint32_t)((first + count + M - 1) / M);
+    float* Pf = nullptr;
+    std::vector<void*> tmp;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(n->stream);
+        for (void* q : tmp) (void)hipFree(q);
+    };
+    if (P) {
+        if (hipMalloc((void**)&Pf, sizeof(float) * n->S) != hipSuccess) return fail(DPSNN_E_NOMEM, "temporary P buffer");
+        tmp.push_back(Pf);
+        hipError_t e = launch_scatter_P(*n, Pf);
+        if (e != hipSuccess) { cleanup(); return fail(DPSNN_E_DEVICE, hipGetErrorString(e)); }
+    }
+    const uint32_t chunk_rows = std::max<uint32_t>(1, (uint32_t)((16ull << 20) / M));
+    const uint32_t crow = std::min<uint32_t>(chunk_rows, i1 - i0);
+    const size_t cs = (size_t)crow * M;
+    uint32_t* d_tgt = nullptr; uint8_t* d_dly = nullptr; float *d_w = nullptr, *d_P = nullptr, *d_D = nullptr;
+    bool ok = true;
+    if (tgt) { ok &= hipMalloc((void**)&d_tgt, cs * 4) == hipSuccess; if (d_tgt) tmp.push_back(d_tgt); }
+    if (dly) { ok &= hipMalloc((void**)&d_dly, cs) == hipSuccess; if (d_dly) tmp.push_back(d_dly); }
+    if (w) { ok &= hipMalloc((void**)&d_w, cs * 4) == hipSuccess; if (d_w) tmp.push_back(d_w); }
+    if (P) { ok &= hipMalloc((void**)&d_P, cs * 4) == hipSuccess; if (d_P) tmp.push_back(d_P); }
+    if (D) { ok &= hipMalloc((void**)&d_D, cs * 4) == hipSuccess; if (d_D) tmp.push_back(d_D); }
+    if (!ok) { cleanup(); return fail(DPSNN_E_NOMEM, "temporary read buffers"); }
+    std::vector<uint32_t> h_tgt(tgt ? cs : 0);
+    std::vector<uint8_t> h_dly(dly ? cs : 0);
+    std::vector<float> h_w(w ? cs : 0), h_P(P ? cs : 0), h_D(D ? cs : 0);
+    for (uint32_t r0 = i0; r0 < i1; r0 += crow) {
+        const uint32_t r1 = std::min<uint32_t>(i1, r0 + crow);
+        hipError_t e = launch_read_rows(*n, r0, r1, Pf, d_tgt, d_dly, d_w, d_P, d_D);
+        if (e != hipSuccess) { cleanup(); return fail(DPSNN_E_DEVICE, hipGetErrorString(e)); }
+        const size_t m = (size_t)(r1 - r0) * M;
+        e = hipStreamSynchronize(n->stream);
+        if (e == hipSuccess && tgt) e = hipMemcpy(h_tgt.data(), d_tgt, m * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && dly) e = hipMemcpy(h_dly.data(), d_dly, m, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && w) e = hipMemcpy(h_w.data(), d_w, m * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && P) e = hipMemcpy(h_P.data(), d_P, m * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && D) e = hipMemcpy(h_D.data(), d_D, m * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) { cleanup(); return fail(DPSNN_E_DEVICE, hipGetErrorString(e)); }
+        // canonical indices covered by this chunk, clipped to the request
+        const uint64_t g0 = std::max<uint64_t>((uint64_t)r0 * M, first);
+        const uint64_t g1 = std::min<uint64_t>((uint64_t)r1 * M, first + count);
+        for (uint64_t g = g0; g < g1; ++g) {
+            const size_t src = (size_t)(g - (uint64_t)r0 * M);
+            const size_t dst = (size_t)(g - first);
+            if (tgt) tgt[dst] = h_tgt[src];
+            if (dly) dly[dst] = h_dly[src];
+            if (w) w[dst] = h_w[src];
+            if (P) P[dst] = h_P[src];
+            if (D) D[dst] = h_D[src];
+        }
+    }
+    cleanup();
+    return DPSNN_OK;
+}
+
+int dpsnn_read_weights(dpsnn_net* h, uint64_t first, uint64_t count, float* w, float* P, float* D) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    return read_rows_common(n, first, count, nullptr, nullptr, w, P, D);
+}
+
+int dpsnn_read_connectivity(dpsnn_net* h, uint64_t first, uint64_t count, uint32_t* target,
+                            uint8_t* delay) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    return read_rows_common(n, first, count, target, delay, nullptr, nullptr, nullptr);
+}
+
+int dpsnn_read_state(dpsnn_net* h, float* v, float* u) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    DPSNN_HIP(hipStreamSynchronize(n->stream));
+    if (v) DPSNN_HIP(hipMemcpy(v, n->v, sizeof(float) * n->d.N, hipMemcpyDeviceToHost));
+    if (u) DPSNN_HIP(hipMemcpy(u, n->u, sizeof(float) * n->d.N, hipMemcpyDeviceToHost));
+    return DPSNN_OK;
+}
+
+int dpsnn_get_stats(dpsnn_net* h, dpsnn_stats* st) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n || !st) return fail(DPSNN_E_INVAL, "NULL argument");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    DPSNN_HIP(hipStreamSynchronize(n->stream));
+    DevStats hs[64];
+    DPSNN_HIP(hipMemcpy(hs, n->stats, sizeof(hs), hipMemcpyDeviceToHost));
+    std::memset(st, 0, sizeof(*st));
+    for (int k = 0; k < 64; ++k) {
+        st->spikes += hs[k].spikes;
+        st->events += hs[k].events;
+        st->ltp_visits += hs[k].ltp_visits;
+        st->events_exc += hs[k].events_exc;
+    }
+    st->steps = n->t;
+    st->consolidations = n->consolidations;
+    for (auto& tt : n->timed) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, tt.a, tt.b) == hipSuccess) {
+            n->ms[tt.kind] += ms;
+            n->nt[tt.kind] += 1;
+        }
+        n->event_pool.push_back(tt.a);
+        n->event_pool.push_back(tt.b);
+    }
+    n->timed.clear();
+    st->ms_ltp = n->ms[0]; st->ms_deliver = n->ms[1]; st->ms_neuron = n->ms[2]; st->ms_wupdate = n->ms[3];
+    st->n_ltp = n->nt[0]; st->n_deliver = n->nt[1]; st->n_neuron = n->nt[2]; st->n_wupdate = n->nt[3];
+    return DPSNN_OK;
+}
+
+int dpsnn_set_stimulus(dpsnn_net* h, const uint32_t* t, const uint32_t* id, const float* mv, size_t cnt) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    if (cnt && (!t || !id || !mv)) return fail(DPSNN_E_INVAL, "NULL stimulus arrays");
+    for (size_t e = 0; e < cnt; ++e) {
+        if (id[e] >= n->d.N) return fail(DPSNN_E_INVAL, "stimulus neuron id out of range");
+        if (!std::isfinite(mv[e]) || std::fabs(mv[e]) > 1e6f) return fail(DPSNN_E_INVAL, "stimulus value out of range");
+    }
+    if (cnt > 0xFFFFFFFFull) return fail(DPSNN_E_INVAL, "too many stimulus entries");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    DPSNN_HIP(hipStreamSynchronize(n->stream));
+    std::vector<size_t> order(cnt);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return t[a] < t[b]; });
+    std::vector<uint32_t> sid(cnt), st(cnt);
+    std::vector<float> smv(cnt);
+    for (size_t e = 0; e < cnt; ++e) {
+        sid[e] = id[order[e]];
+        smv[e] = mv[order[e]];
+        st[e] = t[order[e]];
+    }
+    // replace the previous list
+    auto drop = [&](void* p) {
+        if (!p) return;
+        for (size_t a = 0; a < n->allocs.size(); ++a) {
+            if (n->allocs[a].p == p) {
+                dfree(*n, p, n->allocs[a].bytes);
+                n->allocs.erase(n->allocs.begin() + (long)a);
+                break;
+            }
+        }
+    };
+    drop(n->stim_id);
+    drop(n->stim_mv);
+    n->stim_id = nullptr;
+    n->stim_mv = nullptr;
+    n->stim_n = 0;
+    n->stim_t_host.clear();
+    if (cnt == 0) return DPSNN_OK;
+    n->stim_id = (uint32_t*)dalloc(*n, sizeof(uint32_t) * cnt);
+    n->stim_mv = (float*)dalloc(*n, sizeof(float) * cnt);
+    if (!n->stim_id || !n->stim_mv) return fail(DPSNN_E_NOMEM, "stimulus buffers");
+    DPSNN_HIP(hipMemcpy(n->stim_id, sid.data(), sizeof(uint32_t) * cnt, hipMemcpyHostToDevice));
+    DPSNN_HIP(hipMemcpy(n->stim_mv, smv.data(), sizeof(float) * cnt, hipMemcpyHostToDevice));
+    n->stim_n = cnt;
+    n->stim_t_host = st;
+    return DPSNN_OK;
+}
+
+int dpsnn_set_timing(dpsnn_net* h, int enable) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    n->timing = enable != 0;
+    return DPSNN_OK;
+}
+
+int dpsnn_set_tuning(dpsnn_net* h, uint32_t key, uint32_t value) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    switch (key) {
+        case 0:
+            if (value != 256 && value != 512 && value != 1024) return fail(DPSNN_E_INVAL, "delivery block must be 256, 512 or 1024");
+            n->deliver_block = value;
+            return DPSNN_OK;
+        case 1:
+            if (value != 256 && value != 512 && value != 1024) return fail(DPSNN_E_INVAL, "LTP block must be 256, 512 or 1024");
+            if (value < ((n->d.W + 63) / 64) * 64) return fail(DPSNN_E_INVAL, "LTP block smaller than the raster words of a column");
+            n->ltp_block = value;
+            return DPSNN_OK;
+        case 2:
+            n->window = value ? 1u : 0u;
+            return DPSNN_OK;
+        case 3:
+            if (value != 1 && value != 2 && value != 4) return fail(DPSNN_E_INVAL, "unroll must be 1, 2 or 4");
+            n->unroll = value;
+            return DPSNN_OK;
+        default:
+            return fail(DPSNN_E_INVAL, "unknown tuning key");
+    }
+}
+
+void dpsnn_destroy(dpsnn_net* h) { release(reinterpret_cast<Net*>(h)); }
+
+}  // extern "C"

@@ -1,0 +1,211 @@
+// Network construction on the device (Sec. 2, "Initial construction of the
+// connectivity infrastructure"; "Distributed generation of reproducible
+// connections").  The paper builds, per process, a database of incoming
+// synapses split into sets by delay, with two all-to-all exchanges; on one
+// GPU the same structure is a local counting sort:
+//   1. k_count_rows: one wavefront per source neuron draws its M synapses and
+//      counts them per delay (segment lengths) and per excitatory target
+//      (in-degrees of the reverse index);
+//   2. k_col_scan / scan_u32: prefix sums give segment and reverse-row offsets;
+//   3. k_fill_rows: the same draws, ranked stably by delay with wave ballots,
+//      are written to their forward positions and reverse slots.
+#include "net.h"
+
+namespace dpsnn {
+
+namespace {
+
+// Mask of the active lanes whose delay equals x, from the five delay-bit
+// ballots (delays are below 32).
+__device__ __forceinline__ unsigned long long same_delay(unsigned long long act,
+                                                         const unsigned long long bb[5],
+                                                         uint32_t x) {
+    unsigned long long m = act;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) m &= ((x >> b) & 1u) ? bb[b] : ~bb[b];
+    return m;
+}
+
+__global__ __launch_bounds__(256) void k_count_rows(Dims d, const uint32_t* __restrict__ colmap,
+                                                    uint32_t* __restrict__ seg_off,
+                                                    uint32_t* __restrict__ indeg) {
+    const uint32_t row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= d.N) return;  // uniform per wavefront
+    const uint32_t lane = lane_id();
+    const uint32_t c = row / d.Ncol;
+    const uint32_t l = row - c * d.Ncol;
+    uint32_t cnt = 0;  // lane L counts synapses of delay L + 1
+    for (uint32_t base = 0; base < d.M; base += 64) {
+        const uint32_t j = base + lane;
+        const bool valid = j < d.M;
+        Syn s{0, 0, 0, false};
+        if (valid) s = draw_synapse(d, colmap, row, j);
+        const unsigned long long act = __ballot(valid);
+        unsigned long long bb[5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b) bb[b] = __ballot(valid && ((s.delay >> b) & 1u));
+        cnt += (uint32_t)__popcll(same_delay(act, bb, lane + 1));
+        if (valid && s.exc) {
+            const uint32_t kg = colmap[c * kSlots + s.slot] * d.Ncol + s.lt;
+            atomicAdd(&indeg[kg], 1u);
+        }
+    }
+    if (lane < d.Dmax) seg_off[(size_t)c * d.segs + lane * d.Ncol + l] = cnt;
+}
+
+// Per column: exclusive prefix over its (delay, neuron) segment lengths plus
+// the column's base position.
+__global__ __launch_bounds__(1024) void k_col_scan(Dims d, uint32_t* __restrict__ seg_off) {
+    __shared__ uint32_t sh[20];
+    const uint32_t c = blockIdx.x;
+    uint32_t* p = seg_off + (size_t)c * d.segs;
+    uint32_t carry = c * d.Ncol * d.M;
+    for (uint32_t b0 = 0; b0 < d.segs; b0 += blockDim.x) {
+        const uint32_t idx = b0 + threadIdx.x;
+        const uint32_t v = idx < d.segs ? p[idx] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_scan(v, sh, tot);
+        if (idx < d.segs) p[idx] = carry + ex;
+        carry += tot;
+    }
+    if (c == d.C - 1 && threadIdx.x == 0) seg_off[(size_t)d.C * d.segs] = d.N * d.M;
+}
+
+template <typename TgtT>
+__global__ __launch_bounds__(256) void k_fill_rows(Dims d, const uint32_t* __restrict__ colmap,
+                                                   const uint32_t* __restrict__ seg_off,
+                                                   TgtT* __restrict__ tgt, float* __restrict__ w,
+                                                   const uint32_t* __restrict__ rowptr,
+                                                   uint32_t* __restrict__ cursor,
+                                                   uint32_t* __restrict__ rev_srcd,
+                                                   uint32_t* __restrict__ rev_fwd) {
+    const uint32_t row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= d.N) return;
+    const uint32_t lane = lane_id();
+    const uint32_t c = row / d.Ncol;
+    const uint32_t l = row - c * d.Ncol;
+    uint32_t placed = 0;  // lane L: synapses of delay L + 1 already placed
+    for (uint32_t base = 0; base < d.M; base += 64) {
+        const uint32_t j = base + lane;
+        const bool valid = j < d.M;
+        Syn s{0, 0, 1, false};
+        if (valid) s = draw_synapse(d, colmap, row, j);
+        const unsigned long long act = __ballot(valid);
+        unsigned long long bb[5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b) bb[b] = __ballot(valid && ((s.delay >> b) & 1u));
+        const unsigned long long mine = same_delay(act, bb, s.delay);
+        const uint32_t rank = (uint32_t)__popcll(mine & lanemask_lt());
+        const uint32_t before = __shfl(placed, (int)(s.delay - 1u), 64);
+        if (valid) {
+            const uint32_t pos =
+                seg_off[(size_t)c * d.segs + (s.delay - 1u) * d.Ncol + l] + before + rank;
+            tgt[pos] = (TgtT)(s.slot * d.Ncol + s.lt);
+            w[pos] = s.exc ? d.w_exc : d.w_inh;
+            if (s.exc) {
+                const uint32_t kg = colmap[c * kSlots + s.slot] * d.Ncol + s.lt;
+                const uint32_t x = rowptr[kg] + atomicAdd(&cursor[kg], 1u);
+                rev_srcd[x] = (s.slot << 22) | (l << 6) | s.delay;
+                rev_fwd[x] = pos;
+            }
+        }
+        placed += (uint32_t)__popcll(same_delay(act, bb, lane + 1));
+    }
+}
+
+__global__ void k_init_state(Dims d, float* __restrict__ v, float* __restrict__ u,
+                             uint32_t* __restrict__ hist, int32_t* __restrict__ t_old,
+                             int32_t* __restrict__ t_last) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.N) return;
+    const uint32_t l = k % d.Ncol;
+    const float b = 0.2f, c = -65.0f;
+    (void)l;
+    v[k] = c;
+    u[k] = b * c;
+    hist[k] = 0u;
+    t_old[k] = kNoSpike;
+    t_last[k] = kNoSpike;
+}
+
+// Device-wide exclusive scan: tiles of blockDim elements.
+__global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict__ in,
+                                                     uint32_t* __restrict__ out,
+                                                     uint32_t* __restrict__ sums, uint32_t n) {
+    __shared__ uint32_t sh[20];
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t v = idx < n ? in[idx] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_scan(v, sh, tot);
+    if (idx < n) out[idx] = ex;
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t* __restrict__ sums, uint32_t nb,
+                                                    uint32_t* __restrict__ out, uint32_t n) {
+    __shared__ uint32_t sh[20];
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
+        const uint32_t idx = b0 + threadIdx.x;
+        const uint32_t v = idx < nb ? sums[idx] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_scan(v, sh, tot);
+        if (idx < nb) sums[idx] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_add(uint32_t* __restrict__ out,
+                                                   const uint32_t* __restrict__ sums, uint32_t n) {
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) out[idx] += sums[blockIdx.x];
+}
+
+}  // namespace
+
+// out[0..count) = exclusive prefix of in, out[count] = total.
+hipError_t scan_u32(Net& n, const uint32_t* in, uint32_t* out, uint32_t count) {
+    const uint32_t bs = 1024;
+    const uint32_t nb = (count + bs - 1) / bs;
+    if (nb == 0) {
+        return hipMemsetAsync(out, 0, sizeof(uint32_t), n.stream);
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(bs), 0, n.stream, in, out, n.scan_tmp, count);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(bs), 0, n.stream, n.scan_tmp, nb, out, count);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(bs), 0, n.stream, out, n.scan_tmp, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(Net& n) {
+    const Dims& d = n.d;
+    hipError_t e;
+    const uint32_t rows_per_block = 4;  // 256 threads, one wavefront per row
+    const uint32_t gb = (d.N + rows_per_block - 1) / rows_per_block;
+    if ((e = hipMemsetAsync(n.cursor, 0, sizeof(uint32_t) * d.N, n.stream)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count_rows, dim3(gb), dim3(256), 0, n.stream, d, n.colmap, n.seg_off,
+                       n.cursor);
+    hipLaunchKernelGGL(k_col_scan, dim3(d.C), dim3(1024), 0, n.stream, d, n.seg_off);
+    if ((e = scan_u32(n, n.cursor, n.rowptr, d.N)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(n.cursor, 0, sizeof(uint32_t) * d.N, n.stream)) != hipSuccess) return e;
+    // every entry is written below; zeroing keeps stray reads in bounds if not
+    if ((e = hipMemsetAsync(n.tgt, 0, (n.tgt16 ? 2 : 4) * (size_t)n.S, n.stream)) != hipSuccess) return e;
+    if (n.S_exc) {
+        if ((e = hipMemsetAsync(n.rev_srcd, 0, 4 * (size_t)n.S_exc, n.stream)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(n.rev_fwd, 0, 4 * (size_t)n.S_exc, n.stream)) != hipSuccess) return e;
+    }
+    if (n.tgt16) {
+        hipLaunchKernelGGL(k_fill_rows<uint16_t>, dim3(gb), dim3(256), 0, n.stream, d, n.colmap,
+                           n.seg_off, (uint16_t*)n.tgt, n.w, n.rowptr, n.cursor, n.rev_srcd,
+                           n.rev_fwd);
+    } else {
+        hipLaunchKernelGGL(k_fill_rows<uint32_t>, dim3(gb), dim3(256), 0, n.stream, d, n.colmap,
+                           n.seg_off, (uint32_t*)n.tgt, n.w, n.rowptr, n.cursor, n.rev_srcd,
+                           n.rev_fwd);
+    }
+    hipLaunchKernelGGL(k_init_state, dim3((d.N + 255) / 256), dim3(256), 0, n.stream, d, n.v, n.u,
+                       n.hist, n.t_old, n.t_last);
+    return hipGetLastError();
+}
+
+}  // namespace dpsnn

@@ -1,0 +1,101 @@
+// Host-side network object of libdpsnn and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "dev_common.h"
+#include "dpsnn.h"
+
+namespace dpsnn {
+
+// Device arrays of one network.  Layout (all device memory):
+//   forward synapses, "column-delay-major": the synapses of column c occupy
+//   [c*Ncol*M, (c+1)*Ncol*M); inside, segment (d, l) holds the synapses of
+//   local neuron l with delay d in ascending j, segments ordered by d then l,
+//   so all sources of a column that share a delay are contiguous.
+//     seg_off[c*segs + (d-1)*Ncol + l] = first position of segment (d, l),
+//     seg_off[C*segs] = N*M (so the end of a segment is the next entry).
+//     tgt[pos] = slot*Ncol + local target (window index); w[pos]; D[pos].
+//   reverse index of excitatory synapses, rows by global target id:
+//     rowptr[k] .. rowptr[k+1]; rev_srcd = slot<<22 | local source<<6 | delay;
+//     rev_fwd = forward position; P = potentiation accumulator.
+//   raster ring: R slots of C*W 64-bit words; stamp s lives in slot s % R.
+struct Net {
+    dpsnn_config cfg;
+    dpsnn_device dev;
+    Dims d;
+    hipStream_t stream = nullptr;
+    uint32_t t = 0;
+    bool tgt16 = true;
+    uint64_t S = 0, S_exc = 0;
+
+    // allocations
+    struct Alloc { void* p; size_t bytes; };
+    std::vector<Alloc> allocs;
+
+    uint32_t* colmap = nullptr;   // [C*13] column reached from c through slot q
+    uint32_t* srcmap = nullptr;   // [C*13] column that reaches c through slot q
+    uint32_t* seg_off = nullptr;  // [C*segs + 1]
+    void* tgt = nullptr;          // uint16_t or uint32_t [S]
+    float* w = nullptr;           // [S]
+    float* Dacc = nullptr;        // [S]
+    uint32_t* rowptr = nullptr;   // [N+1]
+    uint32_t* cursor = nullptr;   // [N] build scratch; ORDERED event cursor afterwards
+    uint32_t* rev_srcd = nullptr; // [S_exc]
+    uint32_t* rev_fwd = nullptr;  // [S_exc]
+    float* Pacc = nullptr;        // [S_exc]
+    float* v = nullptr;
+    float* u = nullptr;
+    void* acc = nullptr;          // long long[N] (FIXED) or float[N]
+    uint32_t* hist = nullptr;     // [N] bit b: spiked at (latest stamp time) - b
+    int32_t* t_old = nullptr;     // [N] latest stamp older than the history window
+    int32_t* t_last = nullptr;    // [N] latest stamp
+    uint64_t* ring = nullptr;     // [R*C*W]
+    float* tp = nullptr;          // [tp_len] LTP amplitudes by dt
+    float* tm = nullptr;          // [tm_len] LTD amplitudes by dt
+    uint32_t tp_len = 0, tm_len = 0;
+    DevStats* stats = nullptr;    // [64] spread counters
+    uint32_t* scan_tmp = nullptr; // block sums of the device-wide scan
+    // ORDERED mode event buffers
+    uint32_t* ev_cnt = nullptr;   // [N]
+    uint32_t* ev_start = nullptr; // [N+1]
+    unsigned long long* ev_key = nullptr;  // [S]
+    float* ev_w = nullptr;        // [S]
+
+    // stimulus, sorted by step (stable)
+    uint32_t* stim_id = nullptr;
+    float* stim_mv = nullptr;
+    size_t stim_n = 0, stim_bytes_id = 0, stim_bytes_mv = 0;
+    std::vector<uint32_t> stim_t_host;
+
+    // host mirrors
+    uint64_t consolidations = 0;
+    uint32_t thal_whole = 0, thal_thr = 0;
+
+    // tuning
+    uint32_t deliver_block = 1024, ltp_block = 512, window = 1, unroll = 4;
+    size_t max_lds = 65536;
+
+    // timing
+    bool timing = false;
+    struct Timed { int kind; hipEvent_t a, b; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+    double ms[4] = {0, 0, 0, 0};
+    uint64_t nt[4] = {0, 0, 0, 0};
+};
+
+// launchers (return hipError_t)
+hipError_t launch_build(Net& n);
+hipError_t launch_step(Net& n, uint32_t t, uint32_t stim_b, uint32_t stim_e);
+hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, float* Pf, uint32_t* tgt_out,
+                            uint8_t* dly_out, float* w_out, float* P_out, float* D_out);
+hipError_t launch_scatter_P(Net& n, float* Pf);
+hipError_t scan_u32(Net& n, const uint32_t* in, uint32_t* out, uint32_t count);
+
+}  // namespace dpsnn

@@ -1,0 +1,684 @@
+// The 1 ms simulation step (Sec. 2, "Mixed time-driven and event driven
+// simulation", loop items 2.1-2.7, and the periodic "long term synaptic
+// plasticity" block of Table 2).
+//
+//   k_ltp      item 2.1: every neuron stamped t potentiates its incoming
+//              excitatory synapses; one workgroup per target column walks the
+//              reverse rows of the column's spiking neurons (contiguous runs).
+//   k_deliver  items 2.3-2.6: one workgroup per source column delivers the
+//              spikes stamped t-d+1 through the column's delay-d synapses,
+//              accumulates the currents of the 13 reachable target columns
+//              in an LDS window, applies LTD, then flushes the window.
+//   k_neuron   item 2.7 plus the thalamic input: Izhikevich update with two
+//              0.5 ms sub-steps, threshold and reset, spike history, and the
+//              raster word of each wavefront written with one ballot.
+//   k_wupdate  every weight_update_period steps: fold P - D into the weights.
+#include "net.h"
+
+namespace dpsnn {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// LTP (item 2.1).  Synapse (p -> k, delay d), post stamp t: the latest spike
+// of p with stamp <= t - d pairs with it, dt = t - d - stamp >= 0 and
+// P += A+ exp(-dt / tau+) (Sec. 2, STDP rule).  hist[p] bit b means p was
+// stamped t - b, so dt = ctz(hist >> d) when a bit remains; t_old holds the
+// latest stamp older than the 32-step window.
+// ---------------------------------------------------------------------------
+template <int U>
+__global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t* __restrict__ ring,
+                                              const uint32_t* __restrict__ hist,
+                                              const int32_t* __restrict__ t_old,
+                                              const uint32_t* __restrict__ rowptr,
+                                              const uint32_t* __restrict__ rev_srcd,
+                                              float* __restrict__ P,
+                                              const uint32_t* __restrict__ srcmap,
+                                              const float* __restrict__ tp, uint32_t tp_len,
+                                              uint32_t allow_stage, DevStats* __restrict__ stats) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t BS = blockDim.x;
+    uint32_t* pref = lds;              // [BS + 1]
+    uint32_t* x0 = pref + BS + 1;      // [BS]
+    uint32_t* sh = x0 + BS;            // [20]
+    uint32_t* smap = sh + 20;          // [13]
+    uint32_t* hwin = smap + 16;        // [13 * Ncol] when staged
+    const uint32_t tid = threadIdx.x;
+    const uint32_t ct = blockIdx.x;
+    const uint64_t* words = ring + ((size_t)(t % d.R) * d.C + ct) * d.W;
+
+    WordRuns wr{0ull, 0ull};
+    if (tid < d.W) wr = word_runs(words, d.W, tid, 0u);
+    const uint32_t cs = (uint32_t)__popcll(wr.starts);
+    const uint32_t ce = (uint32_t)__popcll(wr.ends);
+    const uint32_t nsp_local = (tid < d.W) ? (uint32_t)__popcll(words[tid]) : 0u;
+    uint32_t nsp;
+    (void)block_scan(nsp_local, sh, nsp);
+    if (nsp == 0) return;  // block-uniform
+    // the k-th run starts at the k-th start bit and ends at the k-th end bit
+    // of the column (runs may span words)
+    uint32_t nruns, nends;
+    const uint32_t bs_ = block_scan(cs, sh, nruns);
+    const uint32_t be_ = block_scan(ce, sh, nends);
+    if (tid < kSlots) smap[tid] = srcmap[ct * kSlots + tid];
+    const bool stage = allow_stage && (nsp * 8u >= d.Ncol);
+    __syncthreads();
+    if (stage) {
+        const uint32_t nwin = kSlots * d.Ncol;
+        for (uint32_t x = tid; x < nwin; x += BS) {
+            const uint32_t q = x / d.Ncol;
+            const uint32_t l = x - q * d.Ncol;
+            hwin[x] = hist[smap[q] * d.Ncol + l];
+        }
+    }
+    unsigned long long visits = 0;
+    for (uint32_t r0 = 0; r0 < nruns; r0 += BS) {
+        {
+            unsigned long long m = wr.starts;
+            for (uint32_t k = 0; k < cs; ++k) {
+                const uint32_t idx = bs_ + k;
+                const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
+                m &= m - 1ull;
+                if (idx >= r0 && idx < r0 + BS) x0[idx - r0] = tid * 64u + b;
+            }
+            m = wr.ends;
+            for (uint32_t k = 0; k < ce; ++k) {
+                const uint32_t idx = be_ + k;
+                const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
+                m &= m - 1ull;
+                if (idx >= r0 && idx < r0 + BS) pref[idx - r0] = tid * 64u + b + 1u;  // exclusive
+            }
+        }
+        __syncthreads();
+        const uint32_t nr = min(BS, nruns - r0);
+        uint32_t a = 0, len = 0;
+        if (tid < nr) {
+            const uint32_t le = min(pref[tid], d.Ncol);
+            const uint32_t ls = min(x0[tid], le);
+            a = rowptr[ct * d.Ncol + ls];
+            len = rowptr[ct * d.Ncol + le] - a;
+        }
+        __syncthreads();
+        uint32_t E;
+        const uint32_t ex = block_scan(len, sh, E);
+        if (tid < nr) {
+            x0[tid] = a;
+            pref[tid] = ex;
+        }
+        __syncthreads();
+        for (uint32_t e0 = 0; e0 < E; e0 += BS * U) {
+            uint32_t xs[U], sd[U];
+            float pv[U];
+            bool ok[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const uint32_t e = e0 + q * BS + tid;
+                ok[q] = e < E;
+                const uint32_t r = ok[q] ? upper_run(pref, nr, e) : 0u;
+                xs[q] = ok[q] ? x0[r] + (e - pref[r]) : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                sd[q] = ok[q] ? rev_srcd[xs[q]] : 0u;
+                pv[q] = ok[q] ? P[xs[q]] : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (!ok[q]) continue;
+                const uint32_t dl = sd[q] & 63u;
+                const uint32_t l = (sd[q] >> 6) & 0xFFFFu;
+                const uint32_t s = sd[q] >> 22;
+                const uint32_t p = smap[s] * d.Ncol + l;
+                const uint32_t h = stage ? hwin[s * d.Ncol + l] : hist[p];
+                const uint32_t m = h >> dl;
+                uint32_t dt;
+                if (m) {
+                    dt = (uint32_t)__ffs((int)m) - 1u;
+                } else {
+                    const int32_t to = t_old[p];
+                    if (to == kNoSpike) continue;
+                    dt = (uint32_t)((int64_t)t - dl - to);
+                }
+                const float a = dt < tp_len ? tp[dt] : 0.0f;
+                P[xs[q]] = pv[q] + a;
+            }
+        }
+        visits += E;
+        __syncthreads();
+    }
+    if (tid == 0) atomicAdd(&stats[ct & 63].ltp_visits, visits);
+}
+
+// ---------------------------------------------------------------------------
+// Delivery, current injection and LTD (items 2.3-2.6).  A spike stamped s
+// reaches the synapses of delay d in step s + d - 1 (its current first moves
+// the target at s + d, "inject W at t_i + D", Sec. 2).  All spiking sources
+// of the column that share a delay occupy contiguous runs of the forward
+// array, so each run is one contiguous stretch of (tgt, w, D).  LTD: the
+// target's latest stamp t_q <= t precedes the arrival at t + 1, dt = t + 1 -
+// t_q, D += A- exp(-dt / tau-).
+// ---------------------------------------------------------------------------
+template <bool FIXED, bool WINDOW, typename TgtT, int U>
+__global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint64_t* __restrict__ ring,
+                                                  const uint32_t* __restrict__ seg_off,
+                                                  const TgtT* __restrict__ tgt,
+                                                  const float* __restrict__ w,
+                                                  float* __restrict__ Dacc,
+                                                  const int32_t* __restrict__ t_last,
+                                                  const uint32_t* __restrict__ colmap,
+                                                  const float* __restrict__ tm, uint32_t tm_len,
+                                                  void* __restrict__ acc_v,
+                                                  DevStats* __restrict__ stats) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ unsigned long long red64[16];
+    const uint32_t BS = blockDim.x;
+    const uint32_t nwin = kSlots * d.Ncol;
+    const size_t win_bytes = WINDOW ? (size_t)nwin * (FIXED ? 8 : 4) : 0;
+    uint32_t* pref = (uint32_t*)(lds_raw + win_bytes);  // [BS + 1]
+    uint32_t* pos0 = pref + BS + 1;                      // [BS]
+    uint32_t* excf = pos0 + BS;                          // [BS]
+    uint32_t* sh = excf + BS;                            // [20]
+    uint32_t* cmap = sh + 20;                            // [13]
+    const uint32_t tid = threadIdx.x;
+    const uint32_t c = blockIdx.x;
+    long long* win64 = (long long*)lds_raw;
+    float* win32 = (float*)lds_raw;
+    long long* acc64 = (long long*)acc_v;
+    float* acc32 = (float*)acc_v;
+
+    if (WINDOW) {
+        for (uint32_t x = tid; x < nwin; x += BS) {
+            if (FIXED) win64[x] = 0; else win32[x] = 0.0f;
+        }
+    }
+    if (tid < kSlots) cmap[tid] = colmap[c * kSlots + tid];
+    __syncthreads();
+
+    const long long q_inh = to_fixed(d.w_inh);
+    const uint32_t split = (d.Ne > 0 && d.Ne < d.Ncol) ? d.Ne : 0u;
+    // tasks (delay, raster word), processed a whole number of delays at a
+    // time so that no run is split between two chunks (the host keeps W <= BS)
+    const uint32_t dpc = max(1u, BS / d.W);
+    unsigned long long events = 0, exc_events = 0;
+    for (uint32_t d0 = 1; d0 <= d.Dmax; d0 += dpc) {
+        const uint32_t nd = min(dpc, d.Dmax - d0 + 1u);
+        const uint32_t dd = d0 + tid / d.W;
+        const uint32_t wd = tid - (tid / d.W) * d.W;
+        const int64_t s = (int64_t)t - (int64_t)dd + 1;
+        const bool live = tid < nd * d.W && s >= 1;
+        WordRuns wr{0ull, 0ull};
+        if (live) {
+            const uint64_t* words = ring + ((size_t)((uint64_t)s % d.R) * d.C + c) * d.W;
+            wr = word_runs(words, d.W, wd, split);
+        }
+        const uint32_t cs = (uint32_t)__popcll(wr.starts);
+        const uint32_t ce = (uint32_t)__popcll(wr.ends);
+        uint32_t nruns, nends;
+        const uint32_t bs_ = block_scan(cs, sh, nruns);
+        const uint32_t be_ = block_scan(ce, sh, nends);
+        for (uint32_t r0 = 0; r0 < nruns; r0 += BS) {
+            // k-th start / k-th end of the chunk form run k (runs never cross a delay)
+            {
+                unsigned long long m = wr.starts;
+                for (uint32_t k = 0; k < cs; ++k) {
+                    const uint32_t idx = bs_ + k;
+                    const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
+                    m &= m - 1ull;
+                    if (idx >= r0 && idx < r0 + BS) {
+                        pos0[idx - r0] = wd * 64u + b;
+                        excf[idx - r0] = dd;
+                    }
+                }
+                m = wr.ends;
+                for (uint32_t k = 0; k < ce; ++k) {
+                    const uint32_t idx = be_ + k;
+                    const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
+                    m &= m - 1ull;
+                    if (idx >= r0 && idx < r0 + BS) pref[idx - r0] = wd * 64u + b + 1u;
+                }
+            }
+            __syncthreads();
+            const uint32_t nr = min(BS, nruns - r0);
+            uint32_t a = 0, len = 0, isx = 0;
+            if (tid < nr) {
+                const uint32_t le = min(pref[tid], d.Ncol);
+                const uint32_t ls = min(pos0[tid], le);
+                const uint32_t rd = min(max(excf[tid], 1u), d.Dmax);
+                const size_t sb = (size_t)c * d.segs + (size_t)(rd - 1u) * d.Ncol;
+                a = seg_off[sb + ls];
+                len = seg_off[sb + le] - a;
+                isx = ls < d.Ne ? 1u : 0u;
+            }
+            __syncthreads();
+            uint32_t E;
+            const uint32_t ex = block_scan(len, sh, E);
+            if (tid < nr) {
+                pos0[tid] = a;
+                excf[tid] = isx;
+                pref[tid] = ex;
+            }
+            __syncthreads();
+            for (uint32_t e0 = 0; e0 < E; e0 += BS * U) {
+                uint32_t pos[U], wi[U];
+                bool ok[U], ex_[U];
+                float wv[U], dv[U];
+                int32_t tl[U];
+                uint32_t kg[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const uint32_t e = e0 + q * BS + tid;
+                    ok[q] = e < E;
+                    const uint32_t r = ok[q] ? upper_run(pref, nr, e) : 0u;
+                    pos[q] = ok[q] ? pos0[r] + (e - pref[r]) : 0u;
+                    ex_[q] = ok[q] && excf[r];
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    wi[q] = ok[q] ? (uint32_t)tgt[pos[q]] : 0u;
+                    wv[q] = ex_[q] ? w[pos[q]] : d.w_inh;
+                    dv[q] = ex_[q] ? Dacc[pos[q]] : 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, wi[q]) : wi[q] / d.Ncol;
+                    kg[q] = cmap[sl] * d.Ncol + (wi[q] - sl * d.Ncol);
+                    tl[q] = ex_[q] ? t_last[kg[q]] : kNoSpike;
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    if (!ok[q]) continue;
+                    exc_events += ex_[q] ? 1u : 0u;
+                    if (WINDOW) {
+                        if (FIXED) {
+                            atomicAdd((unsigned long long*)&win64[wi[q]],
+                                      (unsigned long long)(ex_[q] ? to_fixed(wv[q]) : q_inh));
+                        } else {
+                            atomicAdd(&win32[wi[q]], wv[q]);
+                        }
+                    } else {
+                        if (FIXED) {
+                            atomicAdd((unsigned long long*)&acc64[kg[q]],
+                                      (unsigned long long)(ex_[q] ? to_fixed(wv[q]) : q_inh));
+                        } else {
+                            atomicAdd(&acc32[kg[q]], wv[q]);
+                        }
+                    }
+                    if (tl[q] != kNoSpike) {
+                        const uint32_t dt = (uint32_t)((int64_t)t + 1 - tl[q]);
+                        Dacc[pos[q]] = dv[q] + (dt < tm_len ? tm[dt] : 0.0f);
+                    }
+                }
+            }
+            events += E;
+            __syncthreads();
+        }
+    }
+    if (WINDOW) {
+        __syncthreads();
+        for (uint32_t x = tid; x < nwin; x += BS) {
+            const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
+            const uint32_t kg = cmap[sl] * d.Ncol + (x - sl * d.Ncol);
+            if (FIXED) {
+                const long long val = win64[x];
+                if (val != 0) atomicAdd((unsigned long long*)&acc64[kg], (unsigned long long)val);
+            } else {
+                const float val = win32[x];
+                if (val != 0.0f) atomicAdd(&acc32[kg], val);
+            }
+        }
+    }
+    __syncthreads();
+    const unsigned long long exc_total = block_sum64(exc_events, red64);
+    if (tid == 0 && events) {
+        atomicAdd(&stats[c & 63].events, events);
+        atomicAdd(&stats[c & 63].events_exc, exc_total);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ORDERED mode: the same deliveries, recorded per target with their canonical
+// key (delay, source id, rank within the source's delay-d synapses, which is
+// ascending j), then folded in key order by the neuron kernel.  PASS 0 counts
+// events per target, PASS 1 writes them and applies LTD.
+// ---------------------------------------------------------------------------
+template <int PASS, typename TgtT>
+__global__ __launch_bounds__(256) void k_deliver_seq(Dims d, uint32_t t, const uint64_t* __restrict__ ring,
+                                                     const uint32_t* __restrict__ seg_off,
+                                                     const TgtT* __restrict__ tgt,
+                                                     const float* __restrict__ w,
+                                                     float* __restrict__ Dacc,
+                                                     const int32_t* __restrict__ t_last,
+                                                     const uint32_t* __restrict__ colmap,
+                                                     const float* __restrict__ tm, uint32_t tm_len,
+                                                     uint32_t* __restrict__ ev_cnt,
+                                                     const uint32_t* __restrict__ ev_start,
+                                                     uint32_t* __restrict__ cursor,
+                                                     unsigned long long* __restrict__ ev_key,
+                                                     float* __restrict__ ev_w,
+                                                     DevStats* __restrict__ stats) {
+    const uint32_t c = blockIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t nwave = blockDim.x >> 6;
+    const uint32_t ntasks = d.Dmax * d.W;
+    unsigned long long events = 0, exc_events = 0;
+    for (uint32_t task = wave; task < ntasks; task += nwave) {
+        const uint32_t dd = task / d.W + 1u;
+        const uint32_t wd = task - (dd - 1u) * d.W;
+        const int64_t s = (int64_t)t - (int64_t)dd + 1;
+        if (s < 1) continue;
+        unsigned long long m = ring[((size_t)((uint64_t)s % d.R) * d.C + c) * d.W + wd];
+        while (m) {
+            const uint32_t l = wd * 64u + (uint32_t)__ffsll((long long)m) - 1u;
+            m &= m - 1ull;
+            const uint32_t i = c * d.Ncol + l;
+            const bool exc = l < d.Ne;
+            const size_t sg = (size_t)c * d.segs + (size_t)(dd - 1u) * d.Ncol + l;
+            const uint32_t p0 = seg_off[sg], p1 = seg_off[sg + 1];
+            for (uint32_t pos = p0 + lane; pos < p1; pos += 64) {
+                const uint32_t wi = (uint32_t)tgt[pos];
+                const uint32_t sl = wi / d.Ncol;
+                const uint32_t kg = colmap[c * kSlots + sl] * d.Ncol + (wi - sl * d.Ncol);
+                if (PASS == 0) {
+                    atomicAdd(&ev_cnt[kg], 1u);
+                } else {
+                    const uint32_t slot = ev_start[kg] + atomicAdd(&cursor[kg], 1u);
+                    ev_key[slot] = ((unsigned long long)dd << 42) |
+                                   ((unsigned long long)i << 16) |
+                                   (unsigned long long)(pos - p0);
+                    ev_w[slot] = exc ? w[pos] : d.w_inh;
+                    if (exc) {
+                        const int32_t tq = t_last[kg];
+                        if (tq != kNoSpike) {
+                            const uint32_t dt = (uint32_t)((int64_t)t + 1 - tq);
+                            Dacc[pos] = Dacc[pos] + (dt < tm_len ? tm[dt] : 0.0f);
+                        }
+                    }
+                }
+            }
+            if (PASS == 1) {
+                events += p1 - p0;
+                if (exc) exc_events += p1 - p0;
+            }
+        }
+    }
+    if (PASS == 1 && lane == 0 && events) {
+        atomicAdd(&stats[c & 63].events, events);
+        atomicAdd(&stats[c & 63].events_exc, exc_events);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Neuron update (item 2.7) with the thalamic input (Sec. 2, reproducible
+// stimulus: a prescribed number of events per ms per column).  The recovery
+// equation is read as u' = a (b v - u) (the printed a (b v - c) has no rest
+// state); v takes two 0.5 ms sub-steps and u one 1 ms step (Sec. 3).
+// One thread per neuron; each wavefront covers one 64-neuron raster word.
+// ---------------------------------------------------------------------------
+template <uint32_t MODE>
+__global__ __launch_bounds__(256) void k_neuron(Dims d, uint32_t t, float* __restrict__ v,
+                                                float* __restrict__ u, void* __restrict__ acc_v,
+                                                uint32_t* __restrict__ hist,
+                                                int32_t* __restrict__ t_old,
+                                                int32_t* __restrict__ t_last,
+                                                uint64_t* __restrict__ ring,
+                                                uint32_t thal_whole, uint32_t thal_thr,
+                                                float thal_mv,
+                                                const uint32_t* __restrict__ stim_id,
+                                                const float* __restrict__ stim_mv,
+                                                uint32_t sb, uint32_t se,
+                                                uint32_t* __restrict__ ev_cnt,
+                                                const uint32_t* __restrict__ ev_start,
+                                                const unsigned long long* __restrict__ ev_key,
+                                                const float* __restrict__ ev_w,
+                                                uint32_t* __restrict__ cursor,
+                                                DevStats* __restrict__ stats) {
+    __shared__ uint32_t wsum[4];
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t wi = gid >> 6;
+    const uint32_t lane = lane_id();
+    const bool wave_ok = wi < d.C * d.W;
+    const uint32_t c = wave_ok ? wi / d.W : 0u;
+    const uint32_t wd = wi - c * d.W;
+    const uint32_t l = wd * 64u + lane;
+    const bool valid = wave_ok && l < d.Ncol;
+    bool fired = false;
+    if (valid) {
+        const uint32_t k = c * d.Ncol + l;
+        // external input: thalamic picks of column c in step t, then stimulus
+        uint32_t y[4] = {c, t, kTagThal, 0u};
+        philox10(y, d.key0, d.key1);
+        const uint32_t n = thal_whole + (y[0] < thal_thr ? 1u : 0u);
+        uint32_t z[4] = {y[0], y[1], y[2], y[3]};
+        long long a64 = 0;
+        float a32 = 0.0f;
+        if (MODE == DPSNN_SUM_FIXED) a64 = ((long long*)acc_v)[k];
+        if (MODE == DPSNN_SUM_ATOMIC) a32 = ((float*)acc_v)[k];
+        const long long q_thal = to_fixed(thal_mv);
+        for (uint32_t p = 0; p < n; ++p) {
+            const uint32_t call = p / 3u, word = 1u + p % 3u;
+            if (word == 1u && call > 0u) {
+                z[0] = c; z[1] = t; z[2] = kTagThal; z[3] = call;
+                philox10(z, d.key0, d.key1);
+            }
+            if (pick(z[word], d.Ncol) == l) {
+                if (MODE == DPSNN_SUM_FIXED) a64 += q_thal;
+                else a32 = a32 + thal_mv;
+            }
+        }
+        for (uint32_t e = sb; e < se; ++e) {
+            if (stim_id[e] == k) {
+                if (MODE == DPSNN_SUM_FIXED) a64 += to_fixed(stim_mv[e]);
+                else a32 = a32 + stim_mv[e];
+            }
+        }
+        if (MODE == DPSNN_SUM_ORDERED) {
+            // canonical-order fold of this step's deliveries
+            const uint32_t b0 = ev_start[k];
+            const uint32_t ne = ev_cnt[k];
+            unsigned long long prev = 0ull;
+            for (uint32_t r = 0; r < ne; ++r) {
+                unsigned long long best = ~0ull;
+                float bw = 0.0f;
+                for (uint32_t x = 0; x < ne; ++x) {
+                    const unsigned long long kk = ev_key[b0 + x];
+                    if (kk > prev && kk < best) { best = kk; bw = ev_w[b0 + x]; }
+                }
+                a32 = a32 + bw;
+                prev = best;
+            }
+            ev_cnt[k] = 0u;
+            cursor[k] = 0u;
+        }
+        const float I = (MODE == DPSNN_SUM_FIXED) ? from_fixed(a64) : a32;
+        const bool rs = l < d.Ne;
+        const float pa = rs ? 0.02f : 0.1f;
+        const float pb = 0.2f;
+        const float pc = -65.0f;
+        const float pd = rs ? 8.0f : 2.0f;
+        float vv = v[k], uu = u[k];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float e = 0.04f * vv;
+            e = e * vv;
+            e = e + 5.0f * vv;
+            e = e + 140.0f;
+            e = e - uu;
+            e = e + I;
+            vv = vv + 0.5f * e;
+        }
+        const float bv = pb * vv;
+        uu = uu + pa * (bv - uu);
+        if (vv >= 30.0f) {
+            vv = pc;
+            uu = uu + pd;
+            fired = true;
+        }
+        v[k] = vv;
+        u[k] = uu;
+        // history: bit b <-> stamp (t + 1) - b after the shift
+        const uint32_t h = hist[k];
+        if (h >> 31) t_old[k] = (int32_t)t - 31;
+        hist[k] = (h << 1) | (fired ? 1u : 0u);
+        if (fired) t_last[k] = (int32_t)t + 1;
+        if (MODE == DPSNN_SUM_FIXED) ((long long*)acc_v)[k] = 0;
+        else ((float*)acc_v)[k] = 0.0f;
+    }
+    const unsigned long long mask = __ballot(fired);
+    const uint32_t wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        if (wave_ok) ring[((size_t)((t + 1u) % d.R) * d.C + c) * d.W + wd] = mask;
+        wsum[wv] = (uint32_t)__popcll(mask);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (uint32_t x = 0; x < (blockDim.x >> 6); ++x) s += wsum[x];
+        if (s) atomicAdd(&stats[blockIdx.x & 63].spikes, (unsigned long long)s);
+    }
+}
+
+// Consolidation: for every excitatory synapse (reverse entry x, forward
+// position f): sd = P - D; w <- clamp(w + (bias + sd), 0, w_max);
+// P <- decay * sd; D <- 0.
+__global__ __launch_bounds__(256) void k_wupdate(uint64_t n, const uint32_t* __restrict__ rev_fwd,
+                                                 float* __restrict__ P, float* __restrict__ Dacc,
+                                                 float* __restrict__ w, float bias, float decay,
+                                                 float wmax) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+        const uint32_t f = rev_fwd[x];
+        const float sd = P[x] - Dacc[f];
+        float nw = w[f] + (bias + sd);
+        if (nw < 0.0f) nw = 0.0f;
+        if (nw > wmax) nw = wmax;
+        w[f] = nw;
+        P[x] = decay * sd;
+        Dacc[f] = 0.0f;
+    }
+}
+
+// Allow the dynamic LDS a launch needs (up to the device limit).
+template <typename K>
+void allow_lds(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bytes);
+}
+
+template <typename TgtT>
+hipError_t launch_deliver(Net& n, uint32_t t) {
+    const Dims& d = n.d;
+    const uint32_t mode = n.cfg.sum_mode;
+    if (mode == DPSNN_SUM_ORDERED) {
+        hipLaunchKernelGGL((k_deliver_seq<0, TgtT>), dim3(d.C), dim3(256), 0, n.stream, d, t, n.ring,
+                           n.seg_off, (const TgtT*)n.tgt, n.w, n.Dacc, n.t_last, n.colmap, n.tm,
+                           n.tm_len, n.ev_cnt, n.ev_start, n.cursor, n.ev_key, n.ev_w, n.stats);
+        hipError_t e = scan_u32(n, n.ev_cnt, n.ev_start, d.N);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_deliver_seq<1, TgtT>), dim3(d.C), dim3(256), 0, n.stream, d, t, n.ring,
+                           n.seg_off, (const TgtT*)n.tgt, n.w, n.Dacc, n.t_last, n.colmap, n.tm,
+                           n.tm_len, n.ev_cnt, n.ev_start, n.cursor, n.ev_key, n.ev_w, n.stats);
+        return hipGetLastError();
+    }
+    const bool fixed = mode == DPSNN_SUM_FIXED;
+    // one thread per raster word of a column and delay chunk
+    const uint32_t BS = std::max<uint32_t>(n.deliver_block, ((d.W + 63) / 64) * 64);
+    const size_t win = (size_t)kSlots * d.Ncol * (fixed ? 8 : 4);
+    const size_t base = ((size_t)3 * BS + 1 + 20 + 16) * sizeof(uint32_t);
+    const bool use_win = n.window && (win + base + 256 <= n.max_lds);
+    const size_t lds = (use_win ? win : 0) + base;
+#define DPSNN_DELIVER(FX, WN, UU)                                                             \
+    do {                                                                                      \
+        allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                          \
+        hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(d.C), dim3(BS), lds, n.stream, \
+                           d, t, n.ring, n.seg_off, (const TgtT*)n.tgt, n.w, n.Dacc, n.t_last, \
+                           n.colmap, n.tm, n.tm_len, n.acc, n.stats);                          \
+    } while (0)
+    if (n.unroll == 1) {
+        if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 1); else DPSNN_DELIVER(true, false, 1); }
+        else { if (use_win) DPSNN_DELIVER(false, true, 1); else DPSNN_DELIVER(false, false, 1); }
+    } else if (n.unroll == 2) {
+        if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 2); else DPSNN_DELIVER(true, false, 2); }
+        else { if (use_win) DPSNN_DELIVER(false, true, 2); else DPSNN_DELIVER(false, false, 2); }
+    } else {
+        if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 4); else DPSNN_DELIVER(true, false, 4); }
+        else { if (use_win) DPSNN_DELIVER(false, true, 4); else DPSNN_DELIVER(false, false, 4); }
+    }
+#undef DPSNN_DELIVER
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Every kernel of one step, in the paper's loop order.  kind: 0 LTP,
+// 1 delivery, 2 neuron, 3 consolidation (for the per-kernel timers).
+static void mark(Net& n, int kind, bool begin) {
+    if (!n.timing) return;
+    if (begin) {
+        Net::Timed tt;
+        tt.kind = kind;
+        if (n.event_pool.size() >= 2) {
+            tt.a = n.event_pool.back(); n.event_pool.pop_back();
+            tt.b = n.event_pool.back(); n.event_pool.pop_back();
+        } else {
+            (void)hipEventCreate(&tt.a);
+            (void)hipEventCreate(&tt.b);
+        }
+        (void)hipEventRecord(tt.a, n.stream);
+        n.timed.push_back(tt);
+    } else {
+        (void)hipEventRecord(n.timed.back().b, n.stream);
+    }
+}
+
+hipError_t launch_step(Net& n, uint32_t t, uint32_t stim_b, uint32_t stim_e) {
+    const Dims& d = n.d;
+    hipError_t e;
+    if (t >= 1) {
+        const uint32_t BS = n.ltp_block;
+        const size_t base = ((size_t)2 * BS + 1 + 20 + 16) * sizeof(uint32_t);
+        const size_t hw = (size_t)kSlots * d.Ncol * sizeof(uint32_t);
+        const uint32_t allow = (base + hw <= n.max_lds) ? 1u : 0u;
+        const size_t lds = base + (allow ? hw : 0);
+        allow_lds(k_ltp<4>, lds);
+        mark(n, 0, true);
+        hipLaunchKernelGGL(k_ltp<4>, dim3(d.C), dim3(BS), lds, n.stream, d, t, n.ring, n.hist,
+                           n.t_old, n.rowptr, n.rev_srcd, n.Pacc, n.srcmap, n.tp, n.tp_len, allow,
+                           n.stats);
+        mark(n, 0, false);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        mark(n, 1, true);
+        e = n.tgt16 ? launch_deliver<uint16_t>(n, t) : launch_deliver<uint32_t>(n, t);
+        mark(n, 1, false);
+        if (e != hipSuccess) return e;
+    }
+    const uint32_t words = d.C * d.W;
+    const uint32_t blocks = (words + 3) / 4;
+    mark(n, 2, true);
+#define DPSNN_NEURON(MD)                                                                          \
+    hipLaunchKernelGGL(k_neuron<MD>, dim3(blocks), dim3(256), 0, n.stream, d, t, n.v, n.u, n.acc, \
+                       n.hist, n.t_old, n.t_last, n.ring, n.thal_whole, n.thal_thr,               \
+                       n.cfg.thalamic_current, n.stim_id, n.stim_mv, stim_b, stim_e, n.ev_cnt,    \
+                       n.ev_start, n.ev_key, n.ev_w, n.cursor, n.stats)
+    if (n.cfg.sum_mode == DPSNN_SUM_FIXED) DPSNN_NEURON(DPSNN_SUM_FIXED);
+    else if (n.cfg.sum_mode == DPSNN_SUM_ATOMIC) DPSNN_NEURON(DPSNN_SUM_ATOMIC);
+    else DPSNN_NEURON(DPSNN_SUM_ORDERED);
+#undef DPSNN_NEURON
+    mark(n, 2, false);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint32_t Tw = n.cfg.weight_update_period;
+    if (Tw && (t + 1) % Tw == 0 && n.S_exc) {
+        const uint64_t blocks_w = std::min<uint64_t>((n.S_exc + 255) / 256, 8192);
+        mark(n, 3, true);
+        hipLaunchKernelGGL(k_wupdate, dim3((uint32_t)blocks_w), dim3(256), 0, n.stream, n.S_exc,
+                           n.rev_fwd, n.Pacc, n.Dacc, n.w, n.cfg.wu_bias, n.cfg.sd_decay,
+                           n.cfg.w_max);
+        mark(n, 3, false);
+        n.consolidations++;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace dpsnn

@@ -41,27 +41,31 @@ def make_config(**over) -> dict:
     return cfg
 
 
+def _preset(base: dict, over: dict) -> dict:
+    cfg = dict(base)
+    cfg.update(over)
+    return make_config(**cfg)
+
+
 def tiny(**over) -> dict:
     """2x2 columns x 1250 neurons, M = 100 (0.5 M synapses), 1000 ms."""
-    return make_config(grid_x=2, grid_y=2, synapses_per_neuron=100, **over)
+    return _preset(dict(grid_x=2, grid_y=2, synapses_per_neuron=100), over)
 
 
 def mid(**over) -> dict:
     """24x24 columns x 1250 neurons (720 k neurons), M = 200 (144 M synapses)."""
-    return make_config(grid_x=24, grid_y=24, synapses_per_neuron=200, **over)
+    return _preset(dict(grid_x=24, grid_y=24, synapses_per_neuron=200), over)
 
 
 def large(**over) -> dict:
     """64x64 columns x 1250 neurons (5.12 M neurons), M = 625 (3.2 G synapses)."""
-    return make_config(grid_x=64, grid_y=64, synapses_per_neuron=625, **over)
+    return _preset(dict(grid_x=64, grid_y=64, synapses_per_neuron=625), over)
 
 
 def paper_shaped(grid=(4, 4), M=200, **over) -> dict:
     """The paper's own scaling workload: 1000-neuron columns, M = 200, 76/12/8/4."""
-    base = dict(grid_x=grid[0], grid_y=grid[1], neurons_per_column=1000,
-                synapses_per_neuron=M, conn_mode=CONN_PAPER)
-    base.update(over)
-    return make_config(**base)
+    return _preset(dict(grid_x=grid[0], grid_y=grid[1], neurons_per_column=1000,
+                        synapses_per_neuron=M, conn_mode=CONN_PAPER), over)
 
 
 WORKLOADS = {

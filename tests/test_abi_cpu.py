@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/dpsnn.h, and validates configurations
+before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1310_8478_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "dpsnn.h")).read()
+    return sorted(set(re.findall(r"\b(dpsnn_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def dp():
+    from paper_1310_8478_amd import dpsnn
+    if not os.path.exists(dpsnn._LIB_PATH):
+        pytest.skip("libdpsnn.so not built")
+    dpsnn.lib()
+    return dpsnn
+
+
+def test_every_declared_symbol_is_exported(dp):
+    names = _declared()
+    assert len(names) >= 15
+    L = C.CDLL(dp._LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(dp.EXPORTS)
+
+
+def test_default_config_and_footprint(dp):
+    b_tiny = dp.footprint_bytes(W.tiny())
+    b_mid = dp.footprint_bytes(W.mid())
+    b_large = dp.footprint_bytes(W.large())
+    assert 5e6 < b_tiny < 5e8
+    assert 2e9 < b_mid < 1e10
+    # 3.2 G synapses: forward (2 + 4 + 4 B) and reverse (4 + 4 + 4 B) tables
+    assert 5e10 < b_large < 8e10
+    assert b_large < 288e9
+
+
+@pytest.mark.parametrize("field,value", [
+    ("grid_x", 0), ("neurons_per_column", 1), ("synapses_per_neuron", 0),
+    ("max_delay", 0), ("max_delay", 32), ("exc_fraction", 0.0), ("conn_mode", 2),
+    ("thalamic_rate", 64.0), ("thalamic_rate", -1.0), ("tau_plus", 0.0),
+    ("w_max", float("nan")), ("sum_mode", 3), ("raster_steps", 5),
+])
+def test_invalid_configs_rejected(dp, field, value):
+    cfg = W.tiny(**{field: value})
+    with pytest.raises(dp.DpsnnError) as ei:
+        dp.footprint_bytes(cfg)
+    assert ei.value.code == dp.E_INVAL
+    assert dp.lib().dpsnn_last_error().decode()
+
+
+def test_size_limits(dp):
+    # 2^32 synapses would overflow 32-bit forward positions
+    with pytest.raises(dp.DpsnnError):
+        dp.footprint_bytes(W.make_config(grid_x=128, grid_y=128, synapses_per_neuron=2000))
+    # 2^26 neurons is the id limit
+    with pytest.raises(dp.DpsnnError):
+        dp.footprint_bytes(W.make_config(grid_x=256, grid_y=256, neurons_per_column=1100,
+                                         synapses_per_neuron=1))

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar: bit-exact raster, weights, P, D, v, u and connectivity in the two
+reproducible summation modes (fixed-point and ordered fp32); statistical
+parity (mean rate within 1 %, weight-histogram L1 <= 0.02) in the unordered
+fp32-atomic mode.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1310_8478_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1310_8478_amd import dpsnn
+    dpsnn.lib()
+    return dpsnn
+
+
+def gpu_run(dp, cfg, T, stim=None, tuning=(), conn=True):
+    net = dp.Network(cfg)
+    try:
+        for k, v in tuning:
+            net.set_tuning(k, v)
+        if stim is not None:
+            net.set_stimulus(*stim)
+        net.step(T)
+        net.sync()
+        tt, ii = net.read_spikes(1, T + 1)
+        syn = net.read_weights()
+        out = dict(tt=tt, ii=ii, w=syn["w"], P=syn["P"], D=syn["D"], stats=net.stats())
+        out["v"], out["u"] = net.read_state()
+        if conn:
+            out["tgt"], out["dly"] = net.read_connectivity()
+        return out
+    finally:
+        net.close()
+
+
+def oracle_run(orc, cfg, T, stim=None):
+    n = orc.Net(cfg, max(T, 1))
+    if stim is not None:
+        n.set_stimulus(*stim)
+    n.run(T)
+    tt, ii = n.raster()
+    s = n.synapses()
+    v, u = n.state()
+    out = dict(tt=tt, ii=ii, w=s["w"], P=s["P"], D=s["D"], tgt=s["tgt"], dly=s["dly"], v=v, u=u,
+               counters=n.counters())
+    n.close()
+    return out
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+def assert_bitexact(g, o, conn=True):
+    assert len(g["tt"]) == len(o["tt"]), (len(g["tt"]), len(o["tt"]))
+    np.testing.assert_array_equal(g["tt"], o["tt"])
+    np.testing.assert_array_equal(g["ii"], o["ii"])
+    if conn:
+        np.testing.assert_array_equal(g["tgt"], o["tgt"])
+        np.testing.assert_array_equal(g["dly"], o["dly"])
+    for k in ("w", "P", "D", "v", "u"):
+        np.testing.assert_array_equal(bits(g[k]), bits(o[k]), err_msg=k)
+
+
+CONN_CASES = {
+    "tiny": W.tiny(),
+    "micro_2x2": W.make_config(grid_x=2, grid_y=2, neurons_per_column=30, synapses_per_neuron=12,
+                               max_delay=6),
+    "grid_5x4": W.make_config(grid_x=5, grid_y=4, neurons_per_column=200, synapses_per_neuron=60),
+    "single_column": W.make_config(grid_x=1, grid_y=1, neurons_per_column=300,
+                                   synapses_per_neuron=40),
+    "paper_6x6": W.paper_shaped(grid=(6, 6), M=200, neurons_per_column=100),
+    "odd_column": W.make_config(grid_x=3, grid_y=2, neurons_per_column=1001, synapses_per_neuron=77,
+                                max_delay=31, seed=99),
+}
+
+
+@pytest.mark.parametrize("name", list(CONN_CASES))
+def test_connectivity_bitexact(dp, orc, name):
+    cfg = CONN_CASES[name]
+    _say(f"connectivity {name}")
+    net = dp.Network(cfg)
+    tgt, dly = net.read_connectivity()
+    w = net.read_weights(P=False, D=False)["w"]
+    net.close()
+    n = orc.Net(cfg, 1)
+    s = n.synapses()
+    n.close()
+    np.testing.assert_array_equal(tgt, s["tgt"])
+    np.testing.assert_array_equal(dly, s["dly"])
+    np.testing.assert_array_equal(bits(w), bits(s["w"]))
+
+
+@pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
+def test_tiny_1000_steps_bitexact(dp, orc, mode):
+    cfg = W.tiny(sum_mode=mode)
+    _say(f"tiny 1000 steps mode {mode}")
+    g = gpu_run(dp, cfg, 1000)
+    o = oracle_run(orc, cfg, 1000)
+    assert len(o["tt"]) > 10000
+    assert_bitexact(g, o)
+    assert g["stats"]["events"] == o["counters"]["events"]
+    assert g["stats"]["spikes"] == o["counters"]["spikes"]
+    assert g["stats"]["ltp_visits"] == o["counters"]["ltp_visits"]
+    assert g["stats"]["consolidations"] == 1
+
+
+@pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
+@pytest.mark.parametrize("seed", [77, 78])
+def test_micro_with_stimulus_bitexact(dp, orc, mode, seed):
+    cfg = W.make_config(grid_x=2, grid_y=2, neurons_per_column=30, synapses_per_neuron=12,
+                        max_delay=6, w_exc_init=9.0, w_inh=-6.0, weight_update_period=40,
+                        thalamic_rate=1.5, sum_mode=mode, seed=seed)
+    T = 120
+    stim = W.stimulus_list(120, T, 150, seed=seed, mv_range=(10.0, 120.0))
+    _say(f"micro stimulus mode {mode} seed {seed}")
+    g = gpu_run(dp, cfg, T, stim=stim)
+    o = oracle_run(orc, cfg, T, stim=stim)
+    assert len(o["tt"]) > 100
+    assert_bitexact(g, o)
+
+
+def test_mid_cut_down_bitexact(dp, orc):
+    # the mid workload's column shape (1250 neurons, M = 200) on a 6x6 grid
+    cfg = W.make_config(grid_x=6, grid_y=6, synapses_per_neuron=200, weight_update_period=100)
+    _say("mid cut-down 6x6 300 steps")
+    g = gpu_run(dp, cfg, 300)
+    o = oracle_run(orc, cfg, 300)
+    assert len(o["tt"]) > 1000
+    assert_bitexact(g, o)
+
+
+TUNINGS = [
+    ((0, 256),), ((0, 512), (3, 1)), ((2, 0),), ((3, 2), (1, 1024)), ((2, 0), (0, 256), (3, 1)),
+]
+
+
+@pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
+def test_launch_shape_invariance(dp, orc, mode):
+    # the paper checks identical spikes for every process count (Sec. 3); here
+    # for every block size, unroll and window choice
+    cfg = W.tiny(sum_mode=mode, weight_update_period=150)
+    T = 300
+    _say(f"launch-shape invariance mode {mode}")
+    ref = gpu_run(dp, cfg, T, conn=False)
+    for tn in TUNINGS:
+        _say(f"  tuning {tn}")
+        g = gpu_run(dp, cfg, T, tuning=tn, conn=False)
+        assert_bitexact(g, ref, conn=False)
+
+
+def test_atomic_mode_statistics(dp, orc):
+    T = 1000
+    cfg_o = W.tiny(sum_mode=W.SUM_ORDERED)
+    cfg_a = W.tiny(sum_mode=W.SUM_ATOMIC)
+    _say("atomic mode statistics")
+    g = gpu_run(dp, cfg_a, T, conn=False)
+    o = oracle_run(orc, cfg_o, T)
+    rate_g = len(g["tt"]) / (5000 * T / 1000.0)
+    rate_o = len(o["tt"]) / (5000 * T / 1000.0)
+    assert abs(rate_g / rate_o - 1.0) <= 0.01, (rate_g, rate_o)
+    exc = (np.repeat(np.arange(5000), 100) % 1250) < 1000
+    hg, _ = np.histogram(g["w"][exc], bins=100, range=(0.0, 10.0))
+    ho, _ = np.histogram(o["w"][exc], bins=100, range=(0.0, 10.0))
+    l1 = np.abs(hg / hg.sum() - ho / ho.sum()).sum()
+    assert l1 <= 0.02, l1
+
+
+def test_counter_invariants(dp):
+    cfg = W.tiny()
+    T = 400
+    _say("counter invariants")
+    g = gpu_run(dp, cfg, T)
+    M = 100
+    dl = g["dly"].reshape(-1, M).astype(np.int64)
+    want = sum(int((dl[i] <= T - s).sum()) for s, i in zip(g["tt"].tolist(), g["ii"].tolist()))
+    assert g["stats"]["events"] == want
+    assert g["stats"]["spikes"] == len(g["tt"])
+    src = np.repeat(np.arange(5000), M)
+    exc = (src % 1250) < 1000
+    indeg = np.bincount(g["tgt"][exc].astype(np.int64), minlength=5000)
+    ltp = int(indeg[g["ii"][g["tt"] <= T - 1]].sum())
+    assert g["stats"]["ltp_visits"] == ltp
+
+
+def test_read_errors(dp):
+    net = dp.Network(W.tiny())
+    try:
+        net.step(30)
+        with pytest.raises(dp.DpsnnError) as e:
+            net.read_spikes(1, 40)
+        assert e.value.code == dp.E_RANGE
+        with pytest.raises(dp.DpsnnError) as e:
+            net.read_weights(5000 * 100 - 5, 10)
+        assert e.value.code == dp.E_RANGE
+        import ctypes as C
+        n = C.c_size_t()
+        rc = dp.lib().dpsnn_read_spikes(net.h, 1, 31, None, None, 0, C.byref(n))
+        assert rc in (0, dp.E_BUFSZ)
+    finally:
+        net.close()
+
+
+def test_mid_full_size_window_bitexact(dp, orc):
+    # full mid workload (720 k neurons, 144 M synapses), first 60 steps
+    cfg = W.mid()
+    T = 60
+    _say("mid full size 60 steps")
+    net = dp.Network(cfg)
+    net.step(T)
+    net.sync()
+    tt, ii = net.read_spikes(1, T + 1)
+    v, u = net.read_state()
+    rng = np.random.default_rng(3)
+    rows = rng.integers(0, 720_000, size=64)
+    conn = [net.read_connectivity(int(r) * 200, 200) for r in rows]
+    wts = [net.read_weights(int(r) * 200, 200) for r in rows]
+    net.close()
+    n = orc.Net(cfg, T)
+    n.run(T)
+    ot, oi = n.raster()
+    ov, ou = n.state()
+    np.testing.assert_array_equal(tt, ot)
+    np.testing.assert_array_equal(ii, oi)
+    np.testing.assert_array_equal(bits(v), bits(ov))
+    np.testing.assert_array_equal(bits(u), bits(ou))
+    for r, (tg, dl), ws in zip(rows, conn, wts):
+        s = n.synapses(int(r) * 200, 200)
+        np.testing.assert_array_equal(tg, s["tgt"])
+        np.testing.assert_array_equal(dl, s["dly"])
+        np.testing.assert_array_equal(bits(ws["D"]), bits(s["D"]))
+        np.testing.assert_array_equal(bits(ws["P"]), bits(s["P"]))
+    n.close()
