@@ -671,8 +671,12 @@ int dpsnn_set_tuning(dpsnn_net* h, uint32_t key, uint32_t value) {
             n->window = value ? 1u : 0u;
             return DPSNN_OK;
         case 3:
-            if (value != 1 && value != 2 && value != 4) return fail(DPSNN_E_INVAL, "unroll must be 1, 2 or 4");
+            if (value != 1 && value != 2 && value != 4 && value != 8)
+                return fail(DPSNN_E_INVAL, "unroll must be 1, 2, 4 or 8");
             n->unroll = value;
+            return DPSNN_OK;
+        case 4:
+            n->age = value ? 1u : 0u;
             return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");

@@ -204,14 +204,41 @@ __device__ __forceinline__ uint32_t nth_bit(unsigned long long m, uint32_t k) {
     return (uint32_t)__ffsll((long long)m) - 1u;
 }
 
-// Largest r in [0, n) with pref[r] <= e (pref ascending, pref[0] = 0).
-__device__ __forceinline__ uint32_t upper_run(const uint32_t* pref, uint32_t n, uint32_t e) {
-    uint32_t lo = 0, hi = n;  // invariant: pref[lo] <= e, answer in [lo, hi)
+// Largest r in [lo, n) with pref[r] <= e, given pref[lo] <= e (pref ascending).
+__device__ __forceinline__ uint32_t upper_run(const uint32_t* pref, uint32_t lo, uint32_t n,
+                                              uint32_t e) {
+    uint32_t hi = n;  // invariant: pref[lo] <= e, answer in [lo, hi)
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (pref[mid] <= e) lo = mid; else hi = mid;
     }
     return lo;
 }
+
+// Event ranges of one wavefront: the block's events [0, E) are cut into one
+// contiguous range per wavefront (a multiple of 64), so each wavefront streams
+// its own stretch of the synapse arrays and follows the runs with a cursor.
+struct WaveRange {
+    uint32_t begin, end;
+};
+
+__device__ __forceinline__ WaveRange wave_range(uint32_t E) {
+    const uint32_t nw = blockDim.x >> 6;
+    const uint32_t wave = threadIdx.x >> 6;
+    const uint32_t per = ((E + nw * 64u - 1u) / (nw * 64u)) * 64u;
+    WaveRange w;
+    w.begin = min(E, wave * per);
+    w.end = min(E, w.begin + per);
+    return w;
+}
+
+// Run of event e for a lane, starting from the wavefront's cursor r (the run
+// of the slice base): the common case is one comparison.
+__device__ __forceinline__ uint32_t lane_run(const uint32_t* pref, uint32_t r, uint32_t nr,
+                                             uint32_t e) {
+    if (r + 1 < nr && pref[r + 1] <= e) return upper_run(pref, r + 1, nr, e);
+    return r;
+}
+
 
 }  // namespace dpsnn

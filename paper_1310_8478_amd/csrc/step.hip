@@ -42,7 +42,8 @@ __global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t
     uint32_t* x0 = pref + BS + 1;      // [BS]
     uint32_t* sh = x0 + BS;            // [20]
     uint32_t* smap = sh + 20;          // [13]
-    uint32_t* hwin = smap + 16;        // [13 * Ncol] when staged
+    float* tph = (float*)(smap + 16);  // [64] first LTP amplitudes
+    uint32_t* hwin = smap + 16 + 64;   // [13 * Ncol] when staged
     const uint32_t tid = threadIdx.x;
     const uint32_t ct = blockIdx.x;
     const uint64_t* words = ring + ((size_t)(t % d.R) * d.C + ct) * d.W;
@@ -61,6 +62,7 @@ __global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t
     const uint32_t bs_ = block_scan(cs, sh, nruns);
     const uint32_t be_ = block_scan(ce, sh, nends);
     if (tid < kSlots) smap[tid] = srcmap[ct * kSlots + tid];
+    if (tid < 64) tph[tid] = tid < tp_len ? tp[tid] : 0.0f;
     const bool stage = allow_stage && (nsp * 8u >= d.Ncol);
     __syncthreads();
     if (stage) {
@@ -106,15 +108,20 @@ __global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t
             pref[tid] = ex;
         }
         __syncthreads();
-        for (uint32_t e0 = 0; e0 < E; e0 += BS * U) {
+        const WaveRange wr_ = wave_range(E);
+        uint32_t cur = wr_.begin < wr_.end ? upper_run(pref, 0u, nr, wr_.begin) : 0u;
+        for (uint32_t eb = wr_.begin; eb < wr_.end; eb += 64u * U) {
             uint32_t xs[U], sd[U];
             float pv[U];
             bool ok[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                const uint32_t e = e0 + q * BS + tid;
-                ok[q] = e < E;
-                const uint32_t r = ok[q] ? upper_run(pref, nr, e) : 0u;
+                const uint32_t sb = eb + q * 64u;
+                const uint32_t e = sb + lane_id();
+                ok[q] = e < wr_.end;
+                if (sb < wr_.end && cur + 1 < nr && pref[cur + 1] <= sb)
+                    cur = upper_run(pref, cur + 1, nr, sb);
+                const uint32_t r = ok[q] ? lane_run(pref, cur, nr, e) : 0u;
                 xs[q] = ok[q] ? x0[r] + (e - pref[r]) : 0u;
             }
 #pragma unroll
@@ -139,7 +146,7 @@ __global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t
                     if (to == kNoSpike) continue;
                     dt = (uint32_t)((int64_t)t - dl - to);
                 }
-                const float a = dt < tp_len ? tp[dt] : 0.0f;
+                const float a = dt < 64u ? tph[dt] : (dt < tp_len ? tp[dt] : 0.0f);
                 P[xs[q]] = pv[q] + a;
             }
         }
@@ -168,13 +175,19 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
                                                   const uint32_t* __restrict__ colmap,
                                                   const float* __restrict__ tm, uint32_t tm_len,
                                                   void* __restrict__ acc_v,
+                                                  uint32_t allow_age,
                                                   DevStats* __restrict__ stats) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ unsigned long long red64[16];
     const uint32_t BS = blockDim.x;
     const uint32_t nwin = kSlots * d.Ncol;
     const size_t win_bytes = WINDOW ? (size_t)nwin * (FIXED ? 8 : 4) : 0;
-    uint32_t* pref = (uint32_t*)(lds_raw + win_bytes);  // [BS + 1]
+    // age window: steps since each reachable target's latest spike, saturated
+    // at 255 (255 also means "never" or "look it up"); staged when the
+    // workgroup has enough events to reuse it
+    uint8_t* age = lds_raw + win_bytes;
+    const size_t age_bytes = allow_age ? (((size_t)nwin + 15) & ~(size_t)15) : 0;
+    uint32_t* pref = (uint32_t*)(lds_raw + win_bytes + age_bytes);  // [BS + 1]
     uint32_t* pos0 = pref + BS + 1;                      // [BS]
     uint32_t* excf = pos0 + BS;                          // [BS]
     uint32_t* sh = excf + BS;                            // [20]
@@ -200,6 +213,7 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
     // time so that no run is split between two chunks (the host keeps W <= BS)
     const uint32_t dpc = max(1u, BS / d.W);
     unsigned long long events = 0, exc_events = 0;
+    bool staged = false;
     for (uint32_t d0 = 1; d0 <= d.Dmax; d0 += dpc) {
         const uint32_t nd = min(dpc, d.Dmax - d0 + 1u);
         const uint32_t dd = d0 + tid / d.W;
@@ -257,8 +271,19 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
                 excf[tid] = isx;
                 pref[tid] = ex;
             }
+            if (allow_age && !staged && E >= nwin) {  // block-uniform
+                for (uint32_t x = tid; x < nwin; x += BS) {
+                    const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
+                    const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
+                    const int64_t ag = (tq == kNoSpike) ? 255 : (int64_t)t - tq;
+                    age[x] = (uint8_t)(ag < 255 ? ag : 255);
+                }
+                staged = true;
+            }
             __syncthreads();
-            for (uint32_t e0 = 0; e0 < E; e0 += BS * U) {
+            const WaveRange wr_ = wave_range(E);
+            uint32_t cur = wr_.begin < wr_.end ? upper_run(pref, 0u, nr, wr_.begin) : 0u;
+            for (uint32_t eb = wr_.begin; eb < wr_.end; eb += 64u * U) {
                 uint32_t pos[U], wi[U];
                 bool ok[U], ex_[U];
                 float wv[U], dv[U];
@@ -266,13 +291,15 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
                 uint32_t kg[U];
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
-                    const uint32_t e = e0 + q * BS + tid;
-                    ok[q] = e < E;
-                    const uint32_t r = ok[q] ? upper_run(pref, nr, e) : 0u;
+                    const uint32_t sb = eb + q * 64u;
+                    const uint32_t e = sb + lane_id();
+                    ok[q] = e < wr_.end;
+                    if (sb < wr_.end && cur + 1 < nr && pref[cur + 1] <= sb)
+                        cur = upper_run(pref, cur + 1, nr, sb);
+                    const uint32_t r = ok[q] ? lane_run(pref, cur, nr, e) : 0u;
                     pos[q] = ok[q] ? pos0[r] + (e - pref[r]) : 0u;
                     ex_[q] = ok[q] && excf[r];
                 }
-#pragma unroll
                 for (int q = 0; q < U; ++q) {
                     wi[q] = ok[q] ? (uint32_t)tgt[pos[q]] : 0u;
                     wv[q] = ex_[q] ? w[pos[q]] : d.w_inh;
@@ -282,7 +309,9 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
                 for (int q = 0; q < U; ++q) {
                     const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, wi[q]) : wi[q] / d.Ncol;
                     kg[q] = cmap[sl] * d.Ncol + (wi[q] - sl * d.Ncol);
-                    tl[q] = ex_[q] ? t_last[kg[q]] : kNoSpike;
+                    const uint32_t ag = (staged && ex_[q]) ? age[wi[q]] : 255u;
+                    tl[q] = !ex_[q] ? kNoSpike
+                                    : (ag < 255u ? (int32_t)(t - ag) : t_last[kg[q]]);
                 }
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
@@ -585,15 +614,18 @@ hipError_t launch_deliver(Net& n, uint32_t t) {
     // one thread per raster word of a column and delay chunk
     const uint32_t BS = std::max<uint32_t>(n.deliver_block, ((d.W + 63) / 64) * 64);
     const size_t win = (size_t)kSlots * d.Ncol * (fixed ? 8 : 4);
+    const size_t agew = (((size_t)kSlots * d.Ncol) + 15) & ~(size_t)15;
     const size_t base = ((size_t)3 * BS + 1 + 20 + 16) * sizeof(uint32_t);
     const bool use_win = n.window && (win + base + 256 <= n.max_lds);
-    const size_t lds = (use_win ? win : 0) + base;
+    const size_t lds0 = (use_win ? win : 0) + base;
+    const uint32_t allow_age = (n.age && lds0 + agew + 256 <= n.max_lds) ? 1u : 0u;
+    const size_t lds = lds0 + (allow_age ? agew : 0);
 #define DPSNN_DELIVER(FX, WN, UU)                                                             \
     do {                                                                                      \
         allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                          \
         hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(d.C), dim3(BS), lds, n.stream, \
                            d, t, n.ring, n.seg_off, (const TgtT*)n.tgt, n.w, n.Dacc, n.t_last, \
-                           n.colmap, n.tm, n.tm_len, n.acc, n.stats);                          \
+                           n.colmap, n.tm, n.tm_len, n.acc, allow_age, n.stats);               \
     } while (0)
     if (n.unroll == 1) {
         if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 1); else DPSNN_DELIVER(true, false, 1); }
@@ -601,9 +633,12 @@ hipError_t launch_deliver(Net& n, uint32_t t) {
     } else if (n.unroll == 2) {
         if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 2); else DPSNN_DELIVER(true, false, 2); }
         else { if (use_win) DPSNN_DELIVER(false, true, 2); else DPSNN_DELIVER(false, false, 2); }
-    } else {
+    } else if (n.unroll == 4) {
         if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 4); else DPSNN_DELIVER(true, false, 4); }
         else { if (use_win) DPSNN_DELIVER(false, true, 4); else DPSNN_DELIVER(false, false, 4); }
+    } else {
+        if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 8); else DPSNN_DELIVER(true, false, 8); }
+        else { if (use_win) DPSNN_DELIVER(false, true, 8); else DPSNN_DELIVER(false, false, 8); }
     }
 #undef DPSNN_DELIVER
     return hipGetLastError();
@@ -637,7 +672,7 @@ hipError_t launch_step(Net& n, uint32_t t, uint32_t stim_b, uint32_t stim_e) {
     hipError_t e;
     if (t >= 1) {
         const uint32_t BS = n.ltp_block;
-        const size_t base = ((size_t)2 * BS + 1 + 20 + 16) * sizeof(uint32_t);
+        const size_t base = ((size_t)2 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
         const size_t hw = (size_t)kSlots * d.Ncol * sizeof(uint32_t);
         const uint32_t allow = (base + hw <= n.max_lds) ? 1u : 0u;
         const size_t lds = base + (allow ? hw : 0);
