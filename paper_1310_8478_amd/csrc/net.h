@@ -78,7 +78,7 @@ struct Net {
     uint32_t thal_whole = 0, thal_thr = 0;
 
     // tuning
-    uint32_t deliver_block = 1024, ltp_block = 512, window = 1, unroll = 8, age = 1;
+    uint32_t deliver_block = 1024, ltp_block = 1024, window = 1, unroll = 8, age = 1;
     size_t max_lds = 65536;
 
     // timing

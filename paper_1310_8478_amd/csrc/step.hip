@@ -74,6 +74,85 @@ __global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t
         }
     }
     unsigned long long visits = 0;
+    if (nsp == d.Ncol) {
+        // every neuron of the column fired: its reverse rows form one block
+        __syncthreads();
+        const uint32_t x_lo = rowptr[ct * d.Ncol];
+        const uint32_t x_hi = rowptr[(ct + 1) * d.Ncol];
+        const uint32_t total = x_hi - x_lo;
+        // LTP of one reverse entry: returns the new P
+        auto ltp_one = [&](uint32_t sd, float pv) -> float {
+            const uint32_t dl = sd & 63u;
+            const uint32_t l = (sd >> 6) & 0xFFFFu;
+            const uint32_t sl = sd >> 22;
+            const uint32_t p = smap[sl] * d.Ncol + l;
+            const uint32_t h = stage ? hwin[sl * d.Ncol + l] : hist[p];
+            const uint32_t m = h >> dl;
+            uint32_t dt;
+            if (m) {
+                dt = (uint32_t)__ffs((int)m) - 1u;
+            } else {
+                const int32_t to = t_old[p];
+                if (to == kNoSpike) return pv;
+                dt = (uint32_t)((int64_t)t - dl - to);
+            }
+            return pv + (dt < 64u ? tph[dt] : (dt < tp_len ? tp[dt] : 0.0f));
+        };
+        const uint32_t a0 = min(x_hi, (x_lo + 3u) & ~3u);
+        const uint32_t a1 = max(a0, x_hi & ~3u);
+        {
+            uint32_t x = 0xFFFFFFFFu;
+            if (tid < a0 - x_lo) x = x_lo + tid;
+            else if (tid >= 64u && tid - 64u < x_hi - a1) x = a1 + (tid - 64u);
+            if (x != 0xFFFFFFFFu) P[x] = ltp_one(rev_srcd[x], P[x]);
+        }
+        constexpr int G = 2;
+        struct Grp {
+            uint32_t x[G];
+            uint4 sd[G];
+            float4 pv[G];
+            bool ok[G];
+        };
+        const uint32_t nq = (a1 - a0) >> 2;
+        const WaveRange wr_ = wave_range(nq);
+        auto load = [&](uint32_t qb, Grp& g) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const uint32_t qi = qb + q * 64u + lane_id();
+                g.ok[q] = qi < wr_.end;
+                g.x[q] = a0 + 4u * (g.ok[q] ? qi : wr_.begin);
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                g.sd[q] = g.ok[q] ? *(const uint4*)(rev_srcd + g.x[q]) : make_uint4(0u, 0u, 0u, 0u);
+                g.pv[q] = g.ok[q] ? *(const float4*)(P + g.x[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        };
+        auto process = [&](Grp& g) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (!g.ok[q]) continue;
+                float4 o;
+                o.x = ltp_one(g.sd[q].x, g.pv[q].x);
+                o.y = ltp_one(g.sd[q].y, g.pv[q].y);
+                o.z = ltp_one(g.sd[q].z, g.pv[q].z);
+                o.w = ltp_one(g.sd[q].w, g.pv[q].w);
+                *(float4*)(P + g.x[q]) = o;
+            }
+        };
+        Grp A, B;
+        if (wr_.begin < wr_.end) load(wr_.begin, A);
+        for (uint32_t qb = wr_.begin; qb < wr_.end; qb += 2u * 64u * G) {
+            const uint32_t nb = qb + 64u * G;
+            if (nb < wr_.end) load(nb, B);
+            process(A);
+            const uint32_t na = nb + 64u * G;
+            if (na < wr_.end) load(na, A);
+            if (nb < wr_.end) process(B);
+        }
+        visits = total;
+        nruns = 0;  // the run loop below has nothing left to do
+    }
     for (uint32_t r0 = 0; r0 < nruns; r0 += BS) {
         {
             unsigned long long m = wr.starts;
@@ -192,6 +271,7 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
     uint32_t* excf = pos0 + BS;                          // [BS]
     uint32_t* sh = excf + BS;                            // [20]
     uint32_t* cmap = sh + 20;                            // [13]
+    float* tmh = (float*)(cmap + 16);                    // [64] first LTD amplitudes
     const uint32_t tid = threadIdx.x;
     const uint32_t c = blockIdx.x;
     long long* win64 = (long long*)lds_raw;
@@ -205,16 +285,165 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
         }
     }
     if (tid < kSlots) cmap[tid] = colmap[c * kSlots + tid];
+    if (tid < 64) tmh[tid] = tid < tm_len ? tm[tid] : 0.0f;
     __syncthreads();
 
     const long long q_inh = to_fixed(d.w_inh);
     const uint32_t split = (d.Ne > 0 && d.Ne < d.Ncol) ? d.Ne : 0u;
+    unsigned long long events = 0, exc_events = 0;
+    bool staged = false;
+
+    // Dense case: every neuron of the column fired in each of the last Dmax
+    // steps, so every synapse of the column delivers and the events are the
+    // column's whole contiguous block of the forward arrays.
+    int full = (t >= d.Dmax) ? 1 : 0;
+    if (full) {
+        const uint32_t tail = d.Ncol - (d.W - 1u) * 64u;
+        const unsigned long long last = tail >= 64u ? ~0ull : ((1ull << tail) - 1ull);
+        for (uint32_t x = tid; x < d.Dmax * d.W; x += BS) {
+            const uint32_t dd = x / d.W + 1u, wd = x - (dd - 1u) * d.W;
+            const uint64_t word =
+                ring[((size_t)((t - dd + 1u) % d.R) * d.C + c) * d.W + wd];
+            if (word != (wd + 1u == d.W ? last : ~0ull)) full = 0;
+        }
+    }
+    full = __syncthreads_and(full);
+    if (full) {
+        const uint32_t cb = c * d.Ncol * d.M;
+        const uint32_t total = d.Ncol * d.M;
+        const size_t s1 = (size_t)c * d.segs;
+        // inhibitory synapses all have delay 1: one range of the d = 1 block
+        const uint32_t inh_lo = d.Ne < d.Ncol ? seg_off[s1 + d.Ne] : cb;
+        const uint32_t inh_hi = d.Ne < d.Ncol ? seg_off[s1 + d.Ncol] : cb;
+        if (allow_age) {
+            for (uint32_t x = tid; x < nwin; x += BS) {
+                const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
+                const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
+                const int64_t ag = (tq == kNoSpike) ? 255 : (int64_t)t - tq;
+                age[x] = (uint8_t)(ag < 255 ? ag : 255);
+            }
+            staged = true;
+        }
+        __syncthreads();
+        // one delivery through forward position p (excitatory flag ex)
+        auto global_id = [&](uint32_t wi) {
+            const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, wi) : wi / d.Ncol;
+            return cmap[sl] * d.Ncol + (wi - sl * d.Ncol);
+        };
+        auto deliver_one = [&](bool ex, uint32_t wi, float wv, float& dv) {
+            exc_events += ex ? 1u : 0u;
+            if (WINDOW) {
+                if (FIXED) {
+                    atomicAdd((unsigned long long*)&win64[wi],
+                              (unsigned long long)(ex ? to_fixed(wv) : q_inh));
+                } else {
+                    atomicAdd(&win32[wi], ex ? wv : d.w_inh);
+                }
+            } else {
+                if (FIXED) {
+                    atomicAdd((unsigned long long*)&acc64[global_id(wi)],
+                              (unsigned long long)(ex ? to_fixed(wv) : q_inh));
+                } else {
+                    atomicAdd(&acc32[global_id(wi)], ex ? wv : d.w_inh);
+                }
+            }
+            if (ex) {
+                const uint32_t ag = staged ? age[wi] : 255u;
+                uint32_t dt = 0xFFFFFFFFu;
+                if (ag < 255u) {
+                    dt = ag + 1u;
+                } else {
+                    const int32_t tq = t_last[global_id(wi)];
+                    if (tq != kNoSpike) dt = (uint32_t)((int64_t)t + 1 - tq);
+                }
+                if (dt != 0xFFFFFFFFu)
+                    dv = dv + (dt < 64u ? tmh[dt] : (dt < tm_len ? tm[dt] : 0.0f));
+            }
+        };
+        auto is_exc = [&](uint32_t p) { return !(p >= inh_lo && p < inh_hi); };
+        // unaligned head and tail (at most 3 positions each), one lane each
+        const uint32_t fin = cb + total;
+        const uint32_t a0 = min(fin, (cb + 3u) & ~3u);
+        const uint32_t a1 = max(a0, fin & ~3u);
+        {
+            uint32_t p = 0xFFFFFFFFu;
+            if (tid < a0 - cb) p = cb + tid;
+            else if (tid >= 64u && tid - 64u < fin - a1) p = a1 + (tid - 64u);
+            if (p != 0xFFFFFFFFu) {
+                const bool ex = is_exc(p);
+                const uint32_t wi = (uint32_t)tgt[p];
+                float dv = ex ? Dacc[p] : 0.0f;
+                deliver_one(ex, wi, ex ? w[p] : d.w_inh, dv);
+                if (ex) Dacc[p] = dv;
+            }
+        }
+        // aligned body: four consecutive positions per lane, vector loads
+        constexpr int G = 2;
+        struct Grp {
+            uint32_t p[G];
+            uint2 ti[G];
+            float4 wv[G], dv[G];
+            bool ok[G];
+            uint32_t exm[G];  // bit k: position p + k is excitatory
+        };
+        const uint32_t nq = (a1 - a0) >> 2;
+        const WaveRange wr_ = wave_range(nq);
+        auto load = [&](uint32_t qb, Grp& g) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                const uint32_t qi = qb + q * 64u + lane_id();
+                g.ok[q] = qi < wr_.end;
+                g.p[q] = a0 + 4u * (g.ok[q] ? qi : wr_.begin);
+                uint32_t m = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) m |= (is_exc(g.p[q] + k) ? 1u : 0u) << k;
+                g.exm[q] = g.ok[q] ? m : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                g.ti[q] = g.ok[q] ? *(const uint2*)(tgt + g.p[q]) : make_uint2(0u, 0u);
+                g.wv[q] = g.exm[q] ? *(const float4*)(w + g.p[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                g.dv[q] = g.exm[q] ? *(const float4*)(Dacc + g.p[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        };
+        auto process = [&](Grp& g) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (!g.ok[q]) continue;
+                const uint32_t m = g.exm[q];
+                uint32_t wi[4];
+                if (sizeof(TgtT) == 2) {
+                    wi[0] = g.ti[q].x & 0xFFFFu; wi[1] = g.ti[q].x >> 16;
+                    wi[2] = g.ti[q].y & 0xFFFFu; wi[3] = g.ti[q].y >> 16;
+                } else {
+                    const uint32_t* tp32 = (const uint32_t*)tgt;
+                    wi[0] = tp32[g.p[q]]; wi[1] = tp32[g.p[q] + 1];
+                    wi[2] = tp32[g.p[q] + 2]; wi[3] = tp32[g.p[q] + 3];
+                }
+                deliver_one(m & 1u, wi[0], g.wv[q].x, g.dv[q].x);
+                deliver_one(m & 2u, wi[1], g.wv[q].y, g.dv[q].y);
+                deliver_one(m & 4u, wi[2], g.wv[q].z, g.dv[q].z);
+                deliver_one(m & 8u, wi[3], g.wv[q].w, g.dv[q].w);
+                if (m) *(float4*)(Dacc + g.p[q]) = g.dv[q];
+            }
+        };
+        Grp A, B;
+        if (wr_.begin < wr_.end) load(wr_.begin, A);
+        for (uint32_t qb = wr_.begin; qb < wr_.end; qb += 2u * 64u * G) {
+            const uint32_t nb = qb + 64u * G;
+            if (nb < wr_.end) load(nb, B);
+            process(A);
+            const uint32_t na = nb + 64u * G;
+            if (na < wr_.end) load(na, A);
+            if (nb < wr_.end) process(B);
+        }
+        events = (tid == 0) ? total : 0u;
+    }
+
     // tasks (delay, raster word), processed a whole number of delays at a
     // time so that no run is split between two chunks (the host keeps W <= BS)
     const uint32_t dpc = max(1u, BS / d.W);
-    unsigned long long events = 0, exc_events = 0;
-    bool staged = false;
-    for (uint32_t d0 = 1; d0 <= d.Dmax; d0 += dpc) {
+    for (uint32_t d0 = 1; !full && d0 <= d.Dmax; d0 += dpc) {
         const uint32_t nd = min(dpc, d.Dmax - d0 + 1u);
         const uint32_t dd = d0 + tid / d.W;
         const uint32_t wd = tid - (tid / d.W) * d.W;
@@ -334,7 +563,7 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
                     }
                     if (tl[q] != kNoSpike) {
                         const uint32_t dt = (uint32_t)((int64_t)t + 1 - tl[q]);
-                        Dacc[pos[q]] = dv[q] + (dt < tm_len ? tm[dt] : 0.0f);
+                        Dacc[pos[q]] = dv[q] + (dt < 64u ? tmh[dt] : (dt < tm_len ? tm[dt] : 0.0f));
                     }
                 }
             }
@@ -615,7 +844,7 @@ hipError_t launch_deliver(Net& n, uint32_t t) {
     const uint32_t BS = std::max<uint32_t>(n.deliver_block, ((d.W + 63) / 64) * 64);
     const size_t win = (size_t)kSlots * d.Ncol * (fixed ? 8 : 4);
     const size_t agew = (((size_t)kSlots * d.Ncol) + 15) & ~(size_t)15;
-    const size_t base = ((size_t)3 * BS + 1 + 20 + 16) * sizeof(uint32_t);
+    const size_t base = ((size_t)3 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
     const bool use_win = n.window && (win + base + 256 <= n.max_lds);
     const size_t lds0 = (use_win ? win : 0) + base;
     const uint32_t allow_age = (n.age && lds0 + agew + 256 <= n.max_lds) ? 1u : 0u;

@@ -146,6 +146,22 @@ def test_mid_cut_down_bitexact(dp, orc):
     assert_bitexact(g, o)
 
 
+@pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
+def test_large_column_dense_regime_bitexact(dp, orc, mode):
+    # the large workload's column shape (1250 neurons, M = 625) on a 2x2 grid:
+    # from about step 86 every neuron fires every step, which drives the
+    # kernels' dense-column paths; a consolidation falls inside that phase
+    cfg = W.make_config(grid_x=2, grid_y=2, synapses_per_neuron=625,
+                        weight_update_period=120, sum_mode=mode)
+    T = 150
+    _say(f"large column shape, dense regime, mode {mode}")
+    g = gpu_run(dp, cfg, T)
+    o = oracle_run(orc, cfg, T)
+    per = np.bincount(o["tt"], minlength=T + 1)
+    assert (per[100:] == 5000).sum() >= 30, "the run must reach the all-firing regime"
+    assert_bitexact(g, o)
+
+
 TUNINGS = [
     ((0, 256),), ((0, 512), (3, 1)), ((2, 0),), ((3, 2), (1, 1024)), ((2, 0), (0, 256), (3, 1)),
 ]
