@@ -35,6 +35,28 @@ BYTES_NEURON = 16 + 16 + 8          # v,u r+w; acc r+w (int64); hist r+w
 BYTES_CONSOLIDATION = 4 + 8 + 8 + 8  # forward index, P, w, D read+write per exc synapse
 
 KERNELS = ("ltp", "deliver", "neuron", "wupdate")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernels_large_hbm_traffic.json")
+
+
+def measured_traffic(workload, steps, warmup, mode, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when that summary is for another command or for kernel
+    sources that have changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["sha256"]:
+            return None
+        if (rec["workload"], rec["steps"], rec["warmup"], rec["sum_mode"]) != (workload, steps, warmup, mode):
+            return None
+        return rec["traffic_bytes_per_launch"].get(kernel)
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _describe(name, cfg):
@@ -168,8 +190,9 @@ def main():
                    "achieved_GBs": round(bytes_k[k] / (ms / 1000.0) / 1e9, 1) if ms > 0 else None}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     ach = kern[dom]["achieved_GBs"]
+    traffic = measured_traffic(args.workload, args.steps, args.warmup, args.mode, f"k_{dom}")
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": traffic,
             "kernel": f"k_{dom}", "avg_launch_us": kern[dom]["avg_us"],
             "algo_bytes_per_launch": kern[dom]["algo_bytes_per_launch"]}
     cpu = None
