@@ -174,7 +174,35 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  * targets' spike ages in delivery (1 on, 0 off). */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 
+/* Online autotuner of the launch shapes (the knobs of dpsnn_set_tuning):
+ * steps the network steps_per_trial steps under each candidate shape, in two
+ * interleaved rounds, and keeps the fastest delivery and LTP shapes.  The
+ * network advances by those steps; its results do not depend on the shapes. */
+int dpsnn_autotune(dpsnn_net *net, uint32_t steps_per_trial);
+
 void dpsnn_destroy(dpsnn_net *net);
+
+/* ---- Batches: many independent networks advanced together ----------------
+ * A batch steps several networks (of any grid size, M, seed and thalamic
+ * rate) with one launch per kernel: every workgroup looks up its network and
+ * column in a device table.  Each network's results are exactly those of its
+ * own run (the draws are keyed by the network's seed and global ids).
+ * Members must share the device and stream, use DPSNN_SUM_FIXED or
+ * DPSNN_SUM_ATOMIC (all the same) and the same target-index width (13 x
+ * neurons_per_column <= 65536 for all or for none).  While in a batch a
+ * network is stepped only through it; its read_* calls work as usual. */
+typedef struct dpsnn_batch dpsnn_batch;
+
+int dpsnn_batch_create(dpsnn_net *const *nets, uint32_t n_nets, dpsnn_batch **out);
+int dpsnn_batch_step(dpsnn_batch *batch, uint32_t n_steps);
+/* Sums of the members' counters; per-kernel timers of the batch's launches. */
+int dpsnn_batch_get_stats(dpsnn_batch *batch, dpsnn_stats *stats);
+int dpsnn_batch_set_timing(dpsnn_batch *batch, int enable);
+int dpsnn_batch_set_tuning(dpsnn_batch *batch, uint32_t key, uint32_t value);
+int dpsnn_batch_autotune(dpsnn_batch *batch, uint32_t steps_per_trial);
+/* Releases the batch's tables; the member networks stay valid and can be
+ * stepped alone again. */
+void dpsnn_batch_destroy(dpsnn_batch *batch);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *dpsnn_last_error(void);

@@ -114,6 +114,7 @@ std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
         sizeof(uint64_t) * (size_t)d.R * d.C * d.W,       // ring
         sizeof(DevStats) * 64,                            // stats
         sizeof(uint32_t) * (N / 1024 + 2),                // scan_tmp
+        sizeof(uint32_t) * 4,                             // t_dev
     };
     if (c->sum_mode == DPSNN_SUM_ORDERED) {
         b.push_back(sizeof(uint32_t) * N);                // ev_cnt
@@ -148,11 +149,7 @@ void release(Net* n) {
     (void)hipStreamSynchronize(n->stream);
     for (auto& a : n->allocs) dfree(*n, a.p, a.bytes);
     n->allocs.clear();
-    for (auto& tt : n->timed) {
-        (void)hipEventDestroy(tt.a);
-        (void)hipEventDestroy(tt.b);
-    }
-    for (auto e : n->event_pool) (void)hipEventDestroy(e);
+    n->timers.release();
     delete n;
 }
 
@@ -215,7 +212,175 @@ int upload(Net& n, T* dst, const std::vector<T>& src) {
     return DPSNN_OK;
 }
 
+// Device allocation through a dpsnn_device (callbacks or hipMalloc), recorded
+// in `track` so that its owner frees it.
+void* dev_alloc(const dpsnn_device& dev, hipStream_t stream, size_t bytes,
+                std::vector<Net::Alloc>* track) {
+    bytes = std::max<size_t>(bytes, 256);
+    void* p = nullptr;
+    if (dev.alloc) {
+        p = dev.alloc(bytes, stream, dev.ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
+    }
+    if (p && track) track->push_back({p, bytes});
+    return p;
+}
+
+// Descriptor tables and block maps of a launch over `cnt` networks.
+int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_device& dev,
+                    hipStream_t stream, std::vector<Net::Alloc>* track) {
+    L.K = cnt;
+    L.max_ncol = 0;
+    L.max_w = 0;
+    L.sum_mode = m[0]->cfg.sum_mode;
+    L.tgt16 = m[0]->tgt16;
+    std::vector<uint2> col, neu;
+    L.bmap_wu.assign(cnt, nullptr);
+    L.n_wu.assign(cnt, 0);
+    std::vector<std::vector<uint2>> wu(cnt);
+    const uint64_t wchunk = 256ull * kWupdateItems;
+    for (uint32_t k = 0; k < cnt; ++k) {
+        const Dims& d = m[k]->d;
+        L.max_ncol = std::max(L.max_ncol, d.Ncol);
+        L.max_w = std::max(L.max_w, d.W);
+        for (uint32_t c = 0; c < d.C; ++c) col.push_back(make_uint2(k, c));
+        for (uint32_t w0 = 0; w0 < d.C * d.W; w0 += 4) neu.push_back(make_uint2(k, w0));
+        const uint64_t nch = (m[k]->S_exc + wchunk - 1) / wchunk;
+        if (nch > 0xFFFFFFFFull) return fail(DPSNN_E_INVAL, "too many consolidation chunks");
+        for (uint64_t q = 0; q < nch; ++q) wu[k].push_back(make_uint2(0u, (uint32_t)q));
+    }
+    L.n_col = (uint32_t)col.size();
+    L.n_neu = (uint32_t)neu.size();
+    L.descs = (NetDesc*)dev_alloc(dev, stream, sizeof(NetDesc) * cnt, track);
+    L.bmap_col = (uint2*)dev_alloc(dev, stream, sizeof(uint2) * col.size(), track);
+    L.bmap_neu = (uint2*)dev_alloc(dev, stream, sizeof(uint2) * neu.size(), track);
+    if (!L.descs || !L.bmap_col || !L.bmap_neu) return fail(DPSNN_E_NOMEM, "launch tables");
+    DPSNN_HIP(hipMemcpyAsync(L.bmap_col, col.data(), sizeof(uint2) * col.size(), hipMemcpyHostToDevice, stream));
+    DPSNN_HIP(hipMemcpyAsync(L.bmap_neu, neu.data(), sizeof(uint2) * neu.size(), hipMemcpyHostToDevice, stream));
+    for (uint32_t k = 0; k < cnt; ++k) {
+        L.n_wu[k] = (uint32_t)wu[k].size();
+        if (!L.n_wu[k]) continue;
+        L.bmap_wu[k] = (uint2*)dev_alloc(dev, stream, sizeof(uint2) * wu[k].size(), track);
+        if (!L.bmap_wu[k]) return fail(DPSNN_E_NOMEM, "launch tables");
+        DPSNN_HIP(hipMemcpyAsync(L.bmap_wu[k], wu[k].data(), sizeof(uint2) * wu[k].size(),
+                                 hipMemcpyHostToDevice, stream));
+    }
+    L.host_descs.resize(cnt);
+    for (uint32_t k = 0; k < cnt; ++k) L.host_descs[k] = m[k]->make_desc();
+    DPSNN_HIP(hipMemcpyAsync(L.descs, L.host_descs.data(), sizeof(NetDesc) * cnt, hipMemcpyHostToDevice, stream));
+    DPSNN_HIP(hipStreamSynchronize(stream));
+    return DPSNN_OK;
+}
+
+int refresh_descs(LaunchSet& L, Net* const* m, hipStream_t stream) {
+    for (uint32_t k = 0; k < L.K; ++k) L.host_descs[k] = m[k]->make_desc();
+    DPSNN_HIP(hipMemcpyAsync(L.descs, L.host_descs.data(), sizeof(NetDesc) * L.K, hipMemcpyHostToDevice, stream));
+    DPSNN_HIP(hipStreamSynchronize(stream));
+    return DPSNN_OK;
+}
+
+int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
+    switch (key) {
+        case 0:
+            if (value != 256 && value != 512 && value != 1024) return fail(DPSNN_E_INVAL, "delivery block must be 256, 512 or 1024");
+            tn.deliver_block = value;
+            return DPSNN_OK;
+        case 1:
+            if (value != 256 && value != 512 && value != 1024) return fail(DPSNN_E_INVAL, "LTP block must be 256, 512 or 1024");
+            tn.ltp_block = value;
+            return DPSNN_OK;
+        case 2:
+            tn.window = value ? 1u : 0u;
+            return DPSNN_OK;
+        case 3:
+            if (value != 1 && value != 2 && value != 4 && value != 8)
+                return fail(DPSNN_E_INVAL, "unroll must be 1, 2, 4 or 8");
+            tn.unroll = value;
+            return DPSNN_OK;
+        case 4:
+            tn.age = value ? 1u : 0u;
+            return DPSNN_OK;
+        default:
+            return fail(DPSNN_E_INVAL, "unknown tuning key");
+    }
+}
+
+// Online autotuner: each candidate shape runs `steps` steps (two interleaved
+// rounds); the fastest delivery shape and the fastest LTP block are kept.
+int autotune(LaunchSet& L, Tuning& tn, Timers& tm, hipStream_t stream, Net* const* m, uint32_t steps) {
+    if (steps == 0) return fail(DPSNN_E_INVAL, "steps_per_trial must be positive");
+    struct Cand { uint32_t block, unroll; };
+    const Cand dcand[] = {{256, 4}, {512, 4}, {1024, 4}, {256, 8}, {512, 8}, {1024, 8}};
+    const uint32_t lcand[] = {256, 512, 1024};
+    const size_t nd = sizeof(dcand) / sizeof(dcand[0]);
+    std::vector<double> dms(nd, 0.0), lms(3, 0.0);
+    std::vector<uint64_t> dn(nd, 0), ln(3, 0);
+    Timers probe;
+    probe.on = true;
+    const Tuning base = tn;
+    for (int round = 0; round < 2; ++round) {
+        for (size_t c = 0; c < nd; ++c) {
+            Tuning trial = base;
+            trial.deliver_block = dcand[c].block;
+            trial.unroll = dcand[c].unroll;
+            trial.ltp_block = lcand[c % 3];
+            for (uint32_t s = 0; s < steps; ++s) {
+                hipError_t e = launch_step_set(L, trial, probe, stream, m);
+                if (e != hipSuccess) { probe.release(); return fail(DPSNN_E_DEVICE, hipGetErrorString(e)); }
+            }
+            if (hipStreamSynchronize(stream) != hipSuccess) { probe.release(); return fail(DPSNN_E_DEVICE, "sync"); }
+            double before[4] = {probe.ms[0], probe.ms[1], probe.ms[2], probe.ms[3]};
+            uint64_t nbefore[4] = {probe.n[0], probe.n[1], probe.n[2], probe.n[3]};
+            probe.collect();
+            dms[c] += probe.ms[1] - before[1];
+            dn[c] += probe.n[1] - nbefore[1];
+            lms[c % 3] += probe.ms[0] - before[0];
+            ln[c % 3] += probe.n[0] - nbefore[0];
+        }
+    }
+    probe.release();
+    size_t bd = 0, bl = 0;
+    for (size_t c = 1; c < nd; ++c)
+        if (dn[c] && (!dn[bd] || dms[c] / dn[c] < dms[bd] / dn[bd])) bd = c;
+    for (size_t c = 1; c < 3; ++c)
+        if (ln[c] && (!ln[bl] || lms[c] / ln[c] < lms[bl] / ln[bl])) bl = c;
+    if (dn[bd]) { tn.deliver_block = dcand[bd].block; tn.unroll = dcand[bd].unroll; }
+    if (ln[bl]) tn.ltp_block = lcand[bl];
+    (void)tm;
+    return DPSNN_OK;
+}
+
 }  // namespace
+
+NetDesc Net::make_desc() const {
+    NetDesc nd;
+    std::memset(&nd, 0, sizeof(nd));
+    nd.d = d;
+    nd.t_ptr = t_dev;
+    nd.colmap = colmap; nd.srcmap = srcmap; nd.seg_off = seg_off; nd.tgt = tgt;
+    nd.w = w; nd.Dacc = Dacc; nd.rowptr = rowptr; nd.rev_srcd = rev_srcd; nd.rev_fwd = rev_fwd;
+    nd.Pacc = Pacc; nd.v = v; nd.u = u; nd.acc = acc; nd.hist = hist; nd.t_old = t_old;
+    nd.t_last = t_last; nd.ring = ring; nd.tp = tp; nd.tm = tm; nd.tp_len = tp_len;
+    nd.tm_len = tm_len; nd.stats = stats; nd.thal_whole = thal_whole; nd.thal_thr = thal_thr;
+    nd.thal_mv = cfg.thalamic_current; nd.stim_t = stim_t; nd.stim_id = stim_id;
+    nd.stim_mv = stim_mv; nd.stim_n = (uint32_t)stim_n;
+    nd.weight_update_period = cfg.weight_update_period; nd.wu_bias = cfg.wu_bias;
+    nd.sd_decay = cfg.sd_decay; nd.w_max = cfg.w_max; nd.S_exc = S_exc;
+    nd.ev_cnt = ev_cnt; nd.ev_start = ev_start; nd.ev_key = ev_key; nd.ev_w = ev_w;
+    nd.cursor = cursor;
+    return nd;
+}
+
+struct dpsnn_batch {
+    std::vector<Net*> members;
+    hipStream_t stream = nullptr;
+    dpsnn_device dev;
+    LaunchSet L;
+    Tuning tune;
+    Timers timers;
+    std::vector<Net::Alloc> allocs;
+};
 
 extern "C" {
 
@@ -288,7 +453,7 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev->device) == hipSuccess &&
         lds > 0)
-        n->max_lds = (size_t)lds;
+        n->tune.max_lds = (size_t)lds;
 
     Dims& d = n->d;
     std::memset(&d, 0, sizeof(d));
@@ -305,8 +470,6 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     const double fl = std::floor(r);
     n->thal_whole = (uint32_t)fl;
     n->thal_thr = (uint32_t)((r - fl) * 4294967296.0);
-    // the LTP block covers one raster word per thread
-    n->ltp_block = std::max<uint32_t>(n->ltp_block, ((dv.W + 63) / 64) * 64);
 
     const std::vector<size_t> sz = array_bytes(cfg, dv);
     std::vector<void*> p(sz.size(), nullptr);
@@ -325,6 +488,7 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     n->v = (float*)p[k++]; n->u = (float*)p[k++]; n->acc = p[k++];
     n->hist = (uint32_t*)p[k++]; n->t_old = (int32_t*)p[k++]; n->t_last = (int32_t*)p[k++];
     n->ring = (uint64_t*)p[k++]; n->stats = (DevStats*)p[k++]; n->scan_tmp = (uint32_t*)p[k++];
+    n->t_dev = (uint32_t*)p[k++];
     if (cfg->sum_mode == DPSNN_SUM_ORDERED) {
         n->ev_cnt = (uint32_t*)p[k++]; n->ev_start = (uint32_t*)p[k++];
         n->ev_key = (unsigned long long*)p[k++]; n->ev_w = (float*)p[k++];
@@ -380,6 +544,7 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     DPSNN_TRY_HIP(hipMemsetAsync(n->acc, 0, accb, n->stream));
     DPSNN_TRY_HIP(hipMemsetAsync(n->ring, 0, sizeof(uint64_t) * (size_t)dv.R * dv.C * dv.W, n->stream));
     DPSNN_TRY_HIP(hipMemsetAsync(n->stats, 0, sizeof(DevStats) * 64, n->stream));
+    DPSNN_TRY_HIP(hipMemsetAsync(n->t_dev, 0, sizeof(uint32_t) * 4, n->stream));
     if (n->ev_cnt) {
         DPSNN_TRY_HIP(hipMemsetAsync(n->ev_cnt, 0, sizeof(uint32_t) * dv.N, n->stream));
         DPSNN_TRY_HIP(hipMemsetAsync(n->ev_start, 0, sizeof(uint32_t) * (dv.N + 1), n->stream));
@@ -394,6 +559,10 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
         release(n);
         return fail(DPSNN_E_DEVICE, "reverse index size mismatch after build");
     }
+    {
+        Net* one[1] = {n};
+        DPSNN_TRY(make_launch_set(n->solo, one, 1, n->dev, n->stream, &n->allocs));
+    }
 #undef DPSNN_TRY
 #undef DPSNN_TRY_HIP
     *out = reinterpret_cast<dpsnn_net*>(n);
@@ -403,20 +572,17 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
 int dpsnn_step(dpsnn_net* h, uint32_t n_steps) {
     Net* n = reinterpret_cast<Net*>(h);
     if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    if (n->in_batch) return fail(DPSNN_E_INVAL, "the network belongs to a batch; step the batch");
     if ((uint64_t)n->t + n_steps >= (1ull << 31)) return fail(DPSNN_E_RANGE, "step count overflow");
     DPSNN_HIP(hipSetDevice(n->dev.device));
-    for (uint32_t s = 0; s < n_steps; ++s) {
-        const uint32_t t = n->t;
-        uint32_t sb = 0, se = 0;
-        if (n->stim_n) {
-            auto lo = std::lower_bound(n->stim_t_host.begin(), n->stim_t_host.end(), t);
-            auto hi = std::upper_bound(lo, n->stim_t_host.end(), t);
-            sb = (uint32_t)(lo - n->stim_t_host.begin());
-            se = (uint32_t)(hi - n->stim_t_host.begin());
-        }
-        DPSNN_HIP(launch_step(*n, t, sb, se));
-        n->t = t + 1;
+    if (n->desc_dirty) {
+        Net* one[1] = {n};
+        int rc = refresh_descs(n->solo, one, n->stream);
+        if (rc) return rc;
+        n->desc_dirty = false;
     }
+    Net* one[1] = {n};
+    for (uint32_t s = 0; s < n_steps; ++s) DPSNN_HIP(launch_step_set(n->solo, n->tune, n->timers, n->stream, one));
     return DPSNN_OK;
 }
 
@@ -583,18 +749,11 @@ int dpsnn_get_stats(dpsnn_net* h, dpsnn_stats* st) {
     }
     st->steps = n->t;
     st->consolidations = n->consolidations;
-    for (auto& tt : n->timed) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, tt.a, tt.b) == hipSuccess) {
-            n->ms[tt.kind] += ms;
-            n->nt[tt.kind] += 1;
-        }
-        n->event_pool.push_back(tt.a);
-        n->event_pool.push_back(tt.b);
-    }
-    n->timed.clear();
-    st->ms_ltp = n->ms[0]; st->ms_deliver = n->ms[1]; st->ms_neuron = n->ms[2]; st->ms_wupdate = n->ms[3];
-    st->n_ltp = n->nt[0]; st->n_deliver = n->nt[1]; st->n_neuron = n->nt[2]; st->n_wupdate = n->nt[3];
+    n->timers.collect();
+    st->ms_ltp = n->timers.ms[0]; st->ms_deliver = n->timers.ms[1];
+    st->ms_neuron = n->timers.ms[2]; st->ms_wupdate = n->timers.ms[3];
+    st->n_ltp = n->timers.n[0]; st->n_deliver = n->timers.n[1];
+    st->n_neuron = n->timers.n[2]; st->n_wupdate = n->timers.n[3];
     return DPSNN_OK;
 }
 
@@ -607,6 +766,7 @@ int dpsnn_set_stimulus(dpsnn_net* h, const uint32_t* t, const uint32_t* id, cons
         if (!std::isfinite(mv[e]) || std::fabs(mv[e]) > 1e6f) return fail(DPSNN_E_INVAL, "stimulus value out of range");
     }
     if (cnt > 0xFFFFFFFFull) return fail(DPSNN_E_INVAL, "too many stimulus entries");
+    if (n->in_batch) return fail(DPSNN_E_INVAL, "set the stimulus before adding the network to a batch");
     DPSNN_HIP(hipSetDevice(n->dev.device));
     DPSNN_HIP(hipStreamSynchronize(n->stream));
     std::vector<size_t> order(cnt);
@@ -630,59 +790,162 @@ int dpsnn_set_stimulus(dpsnn_net* h, const uint32_t* t, const uint32_t* id, cons
             }
         }
     };
+    drop(n->stim_t);
     drop(n->stim_id);
     drop(n->stim_mv);
+    n->stim_t = nullptr;
     n->stim_id = nullptr;
     n->stim_mv = nullptr;
     n->stim_n = 0;
-    n->stim_t_host.clear();
+    n->desc_dirty = true;
     if (cnt == 0) return DPSNN_OK;
+    n->stim_t = (uint32_t*)dalloc(*n, sizeof(uint32_t) * cnt);
     n->stim_id = (uint32_t*)dalloc(*n, sizeof(uint32_t) * cnt);
     n->stim_mv = (float*)dalloc(*n, sizeof(float) * cnt);
-    if (!n->stim_id || !n->stim_mv) return fail(DPSNN_E_NOMEM, "stimulus buffers");
+    if (!n->stim_t || !n->stim_id || !n->stim_mv) return fail(DPSNN_E_NOMEM, "stimulus buffers");
+    DPSNN_HIP(hipMemcpy(n->stim_t, st.data(), sizeof(uint32_t) * cnt, hipMemcpyHostToDevice));
     DPSNN_HIP(hipMemcpy(n->stim_id, sid.data(), sizeof(uint32_t) * cnt, hipMemcpyHostToDevice));
     DPSNN_HIP(hipMemcpy(n->stim_mv, smv.data(), sizeof(float) * cnt, hipMemcpyHostToDevice));
     n->stim_n = cnt;
-    n->stim_t_host = st;
     return DPSNN_OK;
 }
 
 int dpsnn_set_timing(dpsnn_net* h, int enable) {
     Net* n = reinterpret_cast<Net*>(h);
     if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
-    n->timing = enable != 0;
+    n->timers.on = enable != 0;
     return DPSNN_OK;
 }
 
 int dpsnn_set_tuning(dpsnn_net* h, uint32_t key, uint32_t value) {
     Net* n = reinterpret_cast<Net*>(h);
     if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
-    switch (key) {
-        case 0:
-            if (value != 256 && value != 512 && value != 1024) return fail(DPSNN_E_INVAL, "delivery block must be 256, 512 or 1024");
-            n->deliver_block = value;
-            return DPSNN_OK;
-        case 1:
-            if (value != 256 && value != 512 && value != 1024) return fail(DPSNN_E_INVAL, "LTP block must be 256, 512 or 1024");
-            if (value < ((n->d.W + 63) / 64) * 64) return fail(DPSNN_E_INVAL, "LTP block smaller than the raster words of a column");
-            n->ltp_block = value;
-            return DPSNN_OK;
-        case 2:
-            n->window = value ? 1u : 0u;
-            return DPSNN_OK;
-        case 3:
-            if (value != 1 && value != 2 && value != 4 && value != 8)
-                return fail(DPSNN_E_INVAL, "unroll must be 1, 2, 4 or 8");
-            n->unroll = value;
-            return DPSNN_OK;
-        case 4:
-            n->age = value ? 1u : 0u;
-            return DPSNN_OK;
-        default:
-            return fail(DPSNN_E_INVAL, "unknown tuning key");
-    }
+    return apply_tuning(n->tune, key, value);
 }
 
-void dpsnn_destroy(dpsnn_net* h) { release(reinterpret_cast<Net*>(h)); }
+int dpsnn_autotune(dpsnn_net* h, uint32_t steps_per_trial) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    if (n->in_batch) return fail(DPSNN_E_INVAL, "the network belongs to a batch; tune the batch");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    Net* one[1] = {n};
+    if (n->desc_dirty) {
+        int rc = refresh_descs(n->solo, one, n->stream);
+        if (rc) return rc;
+        n->desc_dirty = false;
+    }
+    return autotune(n->solo, n->tune, n->timers, n->stream, one, steps_per_trial);
+}
+
+void dpsnn_destroy(dpsnn_net* h) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (n && n->in_batch) {
+        fail(DPSNN_E_INVAL, "destroying a network that belongs to a batch");
+        return;
+    }
+    release(n);
+}
+
+int dpsnn_batch_create(dpsnn_net* const* nets, uint32_t n_nets, dpsnn_batch** out) {
+    if (!out) return fail(DPSNN_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!nets || n_nets == 0) return fail(DPSNN_E_INVAL, "a batch needs at least one network");
+    std::vector<Net*> m(n_nets);
+    for (uint32_t k = 0; k < n_nets; ++k) {
+        m[k] = reinterpret_cast<Net*>(nets[k]);
+        if (!m[k]) return fail(DPSNN_E_INVAL, "NULL network in batch");
+        if (m[k]->in_batch) return fail(DPSNN_E_INVAL, "a network is already in a batch");
+        for (uint32_t q = 0; q < k; ++q)
+            if (m[q] == m[k]) return fail(DPSNN_E_INVAL, "a network appears twice in the batch");
+        if (m[k]->dev.device != m[0]->dev.device || m[k]->stream != m[0]->stream)
+            return fail(DPSNN_E_INVAL, "batch members must share device and stream");
+        if (m[k]->cfg.sum_mode != m[0]->cfg.sum_mode || m[k]->tgt16 != m[0]->tgt16)
+            return fail(DPSNN_E_INVAL, "batch members must share summation mode and target width");
+    }
+    if (m[0]->cfg.sum_mode == DPSNN_SUM_ORDERED)
+        return fail(DPSNN_E_INVAL, "ORDERED summation runs one network at a time");
+    DPSNN_HIP(hipSetDevice(m[0]->dev.device));
+    dpsnn_batch* b = new dpsnn_batch();
+    b->members = m;
+    b->stream = m[0]->stream;
+    b->dev = m[0]->dev;
+    b->tune = m[0]->tune;
+    int rc = make_launch_set(b->L, b->members.data(), n_nets, b->dev, b->stream, &b->allocs);
+    if (rc) {
+        for (auto& a : b->allocs) {
+            if (b->dev.free) b->dev.free(a.p, a.bytes, b->stream, b->dev.ctx); else (void)hipFree(a.p);
+        }
+        delete b;
+        return rc;
+    }
+    for (Net* x : m) x->in_batch = true;
+    *out = b;
+    return DPSNN_OK;
+}
+
+int dpsnn_batch_step(dpsnn_batch* b, uint32_t n_steps) {
+    if (!b) return fail(DPSNN_E_INVAL, "batch is NULL");
+    for (Net* x : b->members)
+        if ((uint64_t)x->t + n_steps >= (1ull << 31)) return fail(DPSNN_E_RANGE, "step count overflow");
+    DPSNN_HIP(hipSetDevice(b->dev.device));
+    int rc = refresh_descs(b->L, b->members.data(), b->stream);
+    if (rc) return rc;
+    for (uint32_t s = 0; s < n_steps; ++s)
+        DPSNN_HIP(launch_step_set(b->L, b->tune, b->timers, b->stream, b->members.data()));
+    return DPSNN_OK;
+}
+
+int dpsnn_batch_get_stats(dpsnn_batch* b, dpsnn_stats* st) {
+    if (!b || !st) return fail(DPSNN_E_INVAL, "NULL argument");
+    std::memset(st, 0, sizeof(*st));
+    for (Net* x : b->members) {
+        dpsnn_stats one;
+        int rc = dpsnn_get_stats(reinterpret_cast<dpsnn_net*>(x), &one);
+        if (rc) return rc;
+        st->steps += one.steps;
+        st->spikes += one.spikes;
+        st->events += one.events;
+        st->ltp_visits += one.ltp_visits;
+        st->consolidations += one.consolidations;
+        st->events_exc += one.events_exc;
+    }
+    b->timers.collect();
+    st->ms_ltp = b->timers.ms[0]; st->ms_deliver = b->timers.ms[1];
+    st->ms_neuron = b->timers.ms[2]; st->ms_wupdate = b->timers.ms[3];
+    st->n_ltp = b->timers.n[0]; st->n_deliver = b->timers.n[1];
+    st->n_neuron = b->timers.n[2]; st->n_wupdate = b->timers.n[3];
+    return DPSNN_OK;
+}
+
+int dpsnn_batch_set_timing(dpsnn_batch* b, int enable) {
+    if (!b) return fail(DPSNN_E_INVAL, "batch is NULL");
+    b->timers.on = enable != 0;
+    return DPSNN_OK;
+}
+
+int dpsnn_batch_set_tuning(dpsnn_batch* b, uint32_t key, uint32_t value) {
+    if (!b) return fail(DPSNN_E_INVAL, "batch is NULL");
+    return apply_tuning(b->tune, key, value);
+}
+
+int dpsnn_batch_autotune(dpsnn_batch* b, uint32_t steps_per_trial) {
+    if (!b) return fail(DPSNN_E_INVAL, "batch is NULL");
+    DPSNN_HIP(hipSetDevice(b->dev.device));
+    int rc = refresh_descs(b->L, b->members.data(), b->stream);
+    if (rc) return rc;
+    return autotune(b->L, b->tune, b->timers, b->stream, b->members.data(), steps_per_trial);
+}
+
+void dpsnn_batch_destroy(dpsnn_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->dev.device);
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& a : b->allocs) {
+        if (b->dev.free) b->dev.free(a.p, a.bytes, b->stream, b->dev.ctx); else (void)hipFree(a.p);
+    }
+    b->timers.release();
+    for (Net* x : b->members) x->in_batch = false;
+    delete b;
+}
 
 }  // extern "C"

@@ -19,6 +19,7 @@ constexpr uint32_t kTagSyn = 0x53594E00u;  // counter word 2 of synapse draws
 constexpr uint32_t kTagThal = 0x5448414Cu; // counter word 2 of thalamic draws
 constexpr int32_t kNoSpike = INT32_MIN;
 constexpr uint32_t kHistBits = 32;         // spike-history window in steps
+constexpr uint32_t kWupdateItems = 16;     // reverse entries per thread in consolidation
 
 // Network dimensions and generation constants, passed by value to kernels.
 struct Dims {
@@ -33,9 +34,53 @@ struct Dims {
     uint32_t ncol_magic;   // ceil(2^32 / Ncol): exact quotient for operands < 2^16
 };
 
-// Device counters, one per network.
+// Device counters of one network, spread over 64 slots to avoid contention.
 struct DevStats {
     unsigned long long spikes, events, ltp_visits, events_exc;
+};
+
+// Everything a kernel needs to know about one network: its dimensions and
+// device arrays.  Kept in device memory; a launch covering several networks
+// maps each workgroup to (network, column or word) through a block table.
+struct NetDesc {
+    Dims d;
+    uint32_t* t_ptr;                 // steps completed (device-resident clock)
+    const uint32_t* colmap;          // [C*13]
+    const uint32_t* srcmap;          // [C*13]
+    const uint32_t* seg_off;         // [C*segs + 1]
+    const void* tgt;                 // uint16_t or uint32_t [S]
+    const float* w;                  // [S]
+    float* Dacc;                     // [S]
+    const uint32_t* rowptr;          // [N+1]
+    const uint32_t* rev_srcd;        // [S_exc]
+    const uint32_t* rev_fwd;         // [S_exc]
+    float* Pacc;                     // [S_exc]
+    float* v;
+    float* u;
+    void* acc;                       // long long or float [N]
+    uint32_t* hist;
+    int32_t* t_old;
+    int32_t* t_last;
+    uint64_t* ring;
+    const float* tp;
+    const float* tm;
+    uint32_t tp_len, tm_len;
+    DevStats* stats;                 // [64]
+    uint32_t thal_whole, thal_thr;
+    float thal_mv;
+    const uint32_t* stim_t;          // sorted steps of the stimulus entries
+    const uint32_t* stim_id;
+    const float* stim_mv;
+    uint32_t stim_n;
+    uint32_t weight_update_period;
+    float wu_bias, sd_decay, w_max;
+    unsigned long long S_exc;
+    // ORDERED mode buffers (null otherwise)
+    uint32_t* ev_cnt;
+    const uint32_t* ev_start;
+    unsigned long long* ev_key;
+    float* ev_w;
+    uint32_t* cursor;
 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, multipliers

@@ -13,6 +13,43 @@
 
 namespace dpsnn {
 
+// Launch-shape knobs; results never depend on them.
+struct Tuning {
+    uint32_t deliver_block = 1024, ltp_block = 1024, window = 1, unroll = 8, age = 1;
+    size_t max_lds = 65536;
+};
+
+// Per-kernel device timers (the paper's per-block profiling, Table 2).
+struct Timers {
+    bool on = false;
+    struct Timed { int kind; hipEvent_t a, b; };
+    std::vector<Timed> pending;
+    std::vector<hipEvent_t> pool;
+    double ms[4] = {0, 0, 0, 0};
+    uint64_t n[4] = {0, 0, 0, 0};
+    void begin(int kind, hipStream_t s);
+    void end(hipStream_t s);
+    void collect();   // after a synchronisation: fold pending events into ms / n
+    void release();
+};
+
+// The device tables of one launch over K networks: their descriptors and
+// block maps (network, column), (network, first raster word), and per network
+// the consolidation chunks.  A single network is a set of one.
+struct LaunchSet {
+    uint32_t K = 0;
+    NetDesc* descs = nullptr;
+    uint2* bmap_col = nullptr;
+    uint32_t n_col = 0;
+    uint2* bmap_neu = nullptr;
+    uint32_t n_neu = 0;
+    std::vector<uint2*> bmap_wu;
+    std::vector<uint32_t> n_wu;
+    uint32_t max_ncol = 0, max_w = 0, sum_mode = 0;
+    bool tgt16 = true;
+    std::vector<NetDesc> host_descs;
+};
+
 // Device arrays of one network.  Layout (all device memory):
 //   forward synapses, "column-delay-major": the synapses of column c occupy
 //   [c*Ncol*M, (c+1)*Ncol*M); inside, segment (d, l) holds the synapses of
@@ -30,14 +67,16 @@ struct Net {
     dpsnn_device dev;
     Dims d;
     hipStream_t stream = nullptr;
-    uint32_t t = 0;
+    uint32_t t = 0;                // host mirror of the device clock
     bool tgt16 = true;
+    bool in_batch = false;
     uint64_t S = 0, S_exc = 0;
 
     // allocations
     struct Alloc { void* p; size_t bytes; };
     std::vector<Alloc> allocs;
 
+    uint32_t* t_dev = nullptr;    // device clock
     uint32_t* colmap = nullptr;   // [C*13] column reached from c through slot q
     uint32_t* srcmap = nullptr;   // [C*13] column that reaches c through slot q
     uint32_t* seg_off = nullptr;  // [C*segs + 1]
@@ -68,31 +107,28 @@ struct Net {
     float* ev_w = nullptr;        // [S]
 
     // stimulus, sorted by step (stable)
+    uint32_t* stim_t = nullptr;
     uint32_t* stim_id = nullptr;
     float* stim_mv = nullptr;
-    size_t stim_n = 0, stim_bytes_id = 0, stim_bytes_mv = 0;
-    std::vector<uint32_t> stim_t_host;
+    size_t stim_n = 0;
 
     // host mirrors
     uint64_t consolidations = 0;
     uint32_t thal_whole = 0, thal_thr = 0;
 
-    // tuning
-    uint32_t deliver_block = 1024, ltp_block = 1024, window = 1, unroll = 8, age = 1;
-    size_t max_lds = 65536;
+    Tuning tune;
+    Timers timers;
+    LaunchSet solo;               // this network alone
+    bool desc_dirty = true;
 
-    // timing
-    bool timing = false;
-    struct Timed { int kind; hipEvent_t a, b; };
-    std::vector<Timed> timed;
-    std::vector<hipEvent_t> event_pool;
-    double ms[4] = {0, 0, 0, 0};
-    uint64_t nt[4] = {0, 0, 0, 0};
+    NetDesc make_desc() const;
 };
 
 // launchers (return hipError_t)
 hipError_t launch_build(Net& n);
-hipError_t launch_step(Net& n, uint32_t t, uint32_t stim_b, uint32_t stim_e);
+// One step of every network of the set; members[k] is the network of slot k.
+hipError_t launch_step_set(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
+                           Net* const* members);
 hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, float* Pf, uint32_t* tgt_out,
                             uint8_t* dly_out, float* w_out, float* P_out, float* D_out);
 hipError_t launch_scatter_P(Net& n, float* Pf);

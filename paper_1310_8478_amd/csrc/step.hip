@@ -27,15 +27,23 @@ namespace {
 // latest stamp older than the 32-step window.
 // ---------------------------------------------------------------------------
 template <int U>
-__global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t* __restrict__ ring,
-                                              const uint32_t* __restrict__ hist,
-                                              const int32_t* __restrict__ t_old,
-                                              const uint32_t* __restrict__ rowptr,
-                                              const uint32_t* __restrict__ rev_srcd,
-                                              float* __restrict__ P,
-                                              const uint32_t* __restrict__ srcmap,
-                                              const float* __restrict__ tp, uint32_t tp_len,
-                                              uint32_t allow_stage, DevStats* __restrict__ stats) {
+__global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
+                                              const uint2* __restrict__ bmap, uint32_t allow_stage) {
+    const uint2 br = bmap[blockIdx.x];
+    const NetDesc& nd = nds[br.x];
+    const Dims d = nd.d;
+    const uint32_t t = *nd.t_ptr;
+    if (t < 1) return;  // no stamp 0: nothing to potentiate in the first step
+    const uint64_t* __restrict__ ring = nd.ring;
+    const uint32_t* __restrict__ hist = nd.hist;
+    const int32_t* __restrict__ t_old = nd.t_old;
+    const uint32_t* __restrict__ rowptr = nd.rowptr;
+    const uint32_t* __restrict__ rev_srcd = nd.rev_srcd;
+    float* __restrict__ P = nd.Pacc;
+    const uint32_t* __restrict__ srcmap = nd.srcmap;
+    const float* __restrict__ tp = nd.tp;
+    const uint32_t tp_len = nd.tp_len;
+    DevStats* __restrict__ stats = nd.stats;
     extern __shared__ uint32_t lds[];
     const uint32_t BS = blockDim.x;
     uint32_t* pref = lds;              // [BS + 1]
@@ -45,7 +53,7 @@ __global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t
     float* tph = (float*)(smap + 16);  // [64] first LTP amplitudes
     uint32_t* hwin = smap + 16 + 64;   // [13 * Ncol] when staged
     const uint32_t tid = threadIdx.x;
-    const uint32_t ct = blockIdx.x;
+    const uint32_t ct = br.y;
     const uint64_t* words = ring + ((size_t)(t % d.R) * d.C + ct) * d.W;
 
     WordRuns wr{0ull, 0ull};
@@ -245,17 +253,25 @@ __global__ __launch_bounds__(1024) void k_ltp(Dims d, uint32_t t, const uint64_t
 // t_q, D += A- exp(-dt / tau-).
 // ---------------------------------------------------------------------------
 template <bool FIXED, bool WINDOW, typename TgtT, int U>
-__global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint64_t* __restrict__ ring,
-                                                  const uint32_t* __restrict__ seg_off,
-                                                  const TgtT* __restrict__ tgt,
-                                                  const float* __restrict__ w,
-                                                  float* __restrict__ Dacc,
-                                                  const int32_t* __restrict__ t_last,
-                                                  const uint32_t* __restrict__ colmap,
-                                                  const float* __restrict__ tm, uint32_t tm_len,
-                                                  void* __restrict__ acc_v,
-                                                  uint32_t allow_age,
-                                                  DevStats* __restrict__ stats) {
+__global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nds,
+                                                  const uint2* __restrict__ bmap,
+                                                  uint32_t allow_age) {
+    const uint2 br = bmap[blockIdx.x];
+    const NetDesc& nd = nds[br.x];
+    const Dims d = nd.d;
+    const uint32_t t = *nd.t_ptr;
+    if (t < 1) return;  // no spike has been stamped yet
+    const uint64_t* __restrict__ ring = nd.ring;
+    const uint32_t* __restrict__ seg_off = nd.seg_off;
+    const TgtT* __restrict__ tgt = (const TgtT*)nd.tgt;
+    const float* __restrict__ w = nd.w;
+    float* __restrict__ Dacc = nd.Dacc;
+    const int32_t* __restrict__ t_last = nd.t_last;
+    const uint32_t* __restrict__ colmap = nd.colmap;
+    const float* __restrict__ tm = nd.tm;
+    const uint32_t tm_len = nd.tm_len;
+    void* __restrict__ acc_v = nd.acc;
+    DevStats* __restrict__ stats = nd.stats;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ unsigned long long red64[16];
     const uint32_t BS = blockDim.x;
@@ -273,7 +289,7 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
     uint32_t* cmap = sh + 20;                            // [13]
     float* tmh = (float*)(cmap + 16);                    // [64] first LTD amplitudes
     const uint32_t tid = threadIdx.x;
-    const uint32_t c = blockIdx.x;
+    const uint32_t c = br.y;
     long long* win64 = (long long*)lds_raw;
     float* win32 = (float*)lds_raw;
     long long* acc64 = (long long*)acc_v;
@@ -600,21 +616,29 @@ __global__ __launch_bounds__(1024) void k_deliver(Dims d, uint32_t t, const uint
 // events per target, PASS 1 writes them and applies LTD.
 // ---------------------------------------------------------------------------
 template <int PASS, typename TgtT>
-__global__ __launch_bounds__(256) void k_deliver_seq(Dims d, uint32_t t, const uint64_t* __restrict__ ring,
-                                                     const uint32_t* __restrict__ seg_off,
-                                                     const TgtT* __restrict__ tgt,
-                                                     const float* __restrict__ w,
-                                                     float* __restrict__ Dacc,
-                                                     const int32_t* __restrict__ t_last,
-                                                     const uint32_t* __restrict__ colmap,
-                                                     const float* __restrict__ tm, uint32_t tm_len,
-                                                     uint32_t* __restrict__ ev_cnt,
-                                                     const uint32_t* __restrict__ ev_start,
-                                                     uint32_t* __restrict__ cursor,
-                                                     unsigned long long* __restrict__ ev_key,
-                                                     float* __restrict__ ev_w,
-                                                     DevStats* __restrict__ stats) {
-    const uint32_t c = blockIdx.x;
+__global__ __launch_bounds__(256) void k_deliver_seq(const NetDesc* __restrict__ nds,
+                                                     const uint2* __restrict__ bmap) {
+    const uint2 br = bmap[blockIdx.x];
+    const NetDesc& nd = nds[br.x];
+    const Dims d = nd.d;
+    const uint32_t t = *nd.t_ptr;
+    if (t < 1) return;
+    const uint64_t* __restrict__ ring = nd.ring;
+    const uint32_t* __restrict__ seg_off = nd.seg_off;
+    const TgtT* __restrict__ tgt = (const TgtT*)nd.tgt;
+    const float* __restrict__ w = nd.w;
+    float* __restrict__ Dacc = nd.Dacc;
+    const int32_t* __restrict__ t_last = nd.t_last;
+    const uint32_t* __restrict__ colmap = nd.colmap;
+    const float* __restrict__ tm = nd.tm;
+    const uint32_t tm_len = nd.tm_len;
+    uint32_t* __restrict__ ev_cnt = nd.ev_cnt;
+    const uint32_t* __restrict__ ev_start = nd.ev_start;
+    uint32_t* __restrict__ cursor = nd.cursor;
+    unsigned long long* __restrict__ ev_key = nd.ev_key;
+    float* __restrict__ ev_w = nd.ev_w;
+    DevStats* __restrict__ stats = nd.stats;
+    const uint32_t c = br.y;
     const uint32_t lane = lane_id();
     const uint32_t wave = threadIdx.x >> 6;
     const uint32_t nwave = blockDim.x >> 6;
@@ -674,26 +698,41 @@ __global__ __launch_bounds__(256) void k_deliver_seq(Dims d, uint32_t t, const u
 // One thread per neuron; each wavefront covers one 64-neuron raster word.
 // ---------------------------------------------------------------------------
 template <uint32_t MODE>
-__global__ __launch_bounds__(256) void k_neuron(Dims d, uint32_t t, float* __restrict__ v,
-                                                float* __restrict__ u, void* __restrict__ acc_v,
-                                                uint32_t* __restrict__ hist,
-                                                int32_t* __restrict__ t_old,
-                                                int32_t* __restrict__ t_last,
-                                                uint64_t* __restrict__ ring,
-                                                uint32_t thal_whole, uint32_t thal_thr,
-                                                float thal_mv,
-                                                const uint32_t* __restrict__ stim_id,
-                                                const float* __restrict__ stim_mv,
-                                                uint32_t sb, uint32_t se,
-                                                uint32_t* __restrict__ ev_cnt,
-                                                const uint32_t* __restrict__ ev_start,
-                                                const unsigned long long* __restrict__ ev_key,
-                                                const float* __restrict__ ev_w,
-                                                uint32_t* __restrict__ cursor,
-                                                DevStats* __restrict__ stats) {
+__global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
+                                                const uint2* __restrict__ bmap) {
+    const uint2 br = bmap[blockIdx.x];
+    const NetDesc& nd = nds[br.x];
+    const Dims d = nd.d;
+    const uint32_t t = *nd.t_ptr;
+    float* __restrict__ v = nd.v;
+    float* __restrict__ u = nd.u;
+    void* __restrict__ acc_v = nd.acc;
+    uint32_t* __restrict__ hist = nd.hist;
+    int32_t* __restrict__ t_old = nd.t_old;
+    int32_t* __restrict__ t_last = nd.t_last;
+    uint64_t* __restrict__ ring = nd.ring;
+    const uint32_t thal_whole = nd.thal_whole, thal_thr = nd.thal_thr;
+    const float thal_mv = nd.thal_mv;
+    const uint32_t* __restrict__ stim_id = nd.stim_id;
+    const float* __restrict__ stim_mv = nd.stim_mv;
+    uint32_t* __restrict__ ev_cnt = nd.ev_cnt;
+    const uint32_t* __restrict__ ev_start = nd.ev_start;
+    const unsigned long long* __restrict__ ev_key = nd.ev_key;
+    const float* __restrict__ ev_w = nd.ev_w;
+    uint32_t* __restrict__ cursor = nd.cursor;
+    DevStats* __restrict__ stats = nd.stats;
+    // stimulus entries of step t: [sb, se) of the step-sorted list
+    uint32_t sb = 0, se = 0;
+    if (nd.stim_n) {
+        uint32_t lo = 0, hi = nd.stim_n;
+        while (lo < hi) { const uint32_t m = (lo + hi) >> 1; if (nd.stim_t[m] < t) lo = m + 1; else hi = m; }
+        sb = lo;
+        hi = nd.stim_n;
+        while (lo < hi) { const uint32_t m = (lo + hi) >> 1; if (nd.stim_t[m] <= t) lo = m + 1; else hi = m; }
+        se = lo;
+    }
     __shared__ uint32_t wsum[4];
-    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t wi = gid >> 6;
+    const uint32_t wi = br.y + (threadIdx.x >> 6);
     const uint32_t lane = lane_id();
     const bool wave_ok = wi < d.C * d.W;
     const uint32_t c = wave_ok ? wi / d.W : 0u;
@@ -792,19 +831,26 @@ __global__ __launch_bounds__(256) void k_neuron(Dims d, uint32_t t, float* __res
     if (threadIdx.x == 0) {
         uint32_t s = 0;
         for (uint32_t x = 0; x < (blockDim.x >> 6); ++x) s += wsum[x];
-        if (s) atomicAdd(&stats[blockIdx.x & 63].spikes, (unsigned long long)s);
+        if (s) atomicAdd(&stats[(br.y >> 2) & 63].spikes, (unsigned long long)s);
     }
 }
 
 // Consolidation: for every excitatory synapse (reverse entry x, forward
 // position f): sd = P - D; w <- clamp(w + (bias + sd), 0, w_max);
 // P <- decay * sd; D <- 0.
-__global__ __launch_bounds__(256) void k_wupdate(uint64_t n, const uint32_t* __restrict__ rev_fwd,
-                                                 float* __restrict__ P, float* __restrict__ Dacc,
-                                                 float* __restrict__ w, float bias, float decay,
-                                                 float wmax) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+__global__ __launch_bounds__(256) void k_wupdate(const NetDesc* __restrict__ nds,
+                                                 const uint2* __restrict__ bmap) {
+    const uint2 br = bmap[blockIdx.x];
+    const NetDesc& nd = nds[br.x];
+    const uint32_t* __restrict__ rev_fwd = nd.rev_fwd;
+    float* __restrict__ P = nd.Pacc;
+    float* __restrict__ Dacc = nd.Dacc;
+    float* __restrict__ w = (float*)nd.w;
+    const float bias = nd.wu_bias, decay = nd.sd_decay, wmax = nd.w_max;
+    const unsigned long long chunk = (unsigned long long)blockDim.x * kWupdateItems;
+    const unsigned long long x0 = (unsigned long long)br.y * chunk;
+    const unsigned long long x1 = min(x0 + chunk, nd.S_exc);
+    for (unsigned long long x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
         const uint32_t f = rev_fwd[x];
         const float sd = P[x] - Dacc[f];
         float nw = w[f] + (bias + sd);
@@ -816,7 +862,11 @@ __global__ __launch_bounds__(256) void k_wupdate(uint64_t n, const uint32_t* __r
     }
 }
 
-// Allow the dynamic LDS a launch needs (up to the device limit).
+// Advance the clock of every network of a launch set by one step.
+__global__ void k_tick(const NetDesc* __restrict__ nds, uint32_t n) {
+    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) *nds[k].t_ptr += 1u;
+}
+
 template <typename K>
 void allow_lds(K kernel, size_t bytes) {
     if (bytes > 65536)
@@ -825,44 +875,43 @@ void allow_lds(K kernel, size_t bytes) {
 }
 
 template <typename TgtT>
-hipError_t launch_deliver(Net& n, uint32_t t) {
-    const Dims& d = n.d;
-    const uint32_t mode = n.cfg.sum_mode;
-    if (mode == DPSNN_SUM_ORDERED) {
-        hipLaunchKernelGGL((k_deliver_seq<0, TgtT>), dim3(d.C), dim3(256), 0, n.stream, d, t, n.ring,
-                           n.seg_off, (const TgtT*)n.tgt, n.w, n.Dacc, n.t_last, n.colmap, n.tm,
-                           n.tm_len, n.ev_cnt, n.ev_start, n.cursor, n.ev_key, n.ev_w, n.stats);
-        hipError_t e = scan_u32(n, n.ev_cnt, n.ev_start, d.N);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_deliver_seq<1, TgtT>), dim3(d.C), dim3(256), 0, n.stream, d, t, n.ring,
-                           n.seg_off, (const TgtT*)n.tgt, n.w, n.Dacc, n.t_last, n.colmap, n.tm,
-                           n.tm_len, n.ev_cnt, n.ev_start, n.cursor, n.ev_key, n.ev_w, n.stats);
+hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, Net* const* members) {
+    if (L.sum_mode == DPSNN_SUM_ORDERED) {
+        // one network only (checked when the set is made)
+        Net& n = *members[0];
+        hipLaunchKernelGGL((k_deliver_seq<0, TgtT>), dim3(L.n_col), dim3(256), 0, stream, L.descs,
+                           L.bmap_col);
+        if (n.t >= 1) {
+            hipError_t e = scan_u32(n, n.ev_cnt, n.ev_start, n.d.N);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((k_deliver_seq<1, TgtT>), dim3(L.n_col), dim3(256), 0, stream, L.descs,
+                           L.bmap_col);
         return hipGetLastError();
     }
-    const bool fixed = mode == DPSNN_SUM_FIXED;
+    const bool fixed = L.sum_mode == DPSNN_SUM_FIXED;
     // one thread per raster word of a column and delay chunk
-    const uint32_t BS = std::max<uint32_t>(n.deliver_block, ((d.W + 63) / 64) * 64);
-    const size_t win = (size_t)kSlots * d.Ncol * (fixed ? 8 : 4);
-    const size_t agew = (((size_t)kSlots * d.Ncol) + 15) & ~(size_t)15;
+    const uint32_t BS = std::max<uint32_t>(tune.deliver_block, ((L.max_w + 63) / 64) * 64);
+    const size_t win = (size_t)kSlots * L.max_ncol * (fixed ? 8 : 4);
+    const size_t agew = (((size_t)kSlots * L.max_ncol) + 15) & ~(size_t)15;
     const size_t base = ((size_t)3 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
-    const bool use_win = n.window && (win + base + 256 <= n.max_lds);
+    const bool use_win = tune.window && (win + base + 256 <= tune.max_lds);
     const size_t lds0 = (use_win ? win : 0) + base;
-    const uint32_t allow_age = (n.age && lds0 + agew + 256 <= n.max_lds) ? 1u : 0u;
+    const uint32_t allow_age = (tune.age && lds0 + agew + 256 <= tune.max_lds) ? 1u : 0u;
     const size_t lds = lds0 + (allow_age ? agew : 0);
-#define DPSNN_DELIVER(FX, WN, UU)                                                             \
-    do {                                                                                      \
-        allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                          \
-        hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(d.C), dim3(BS), lds, n.stream, \
-                           d, t, n.ring, n.seg_off, (const TgtT*)n.tgt, n.w, n.Dacc, n.t_last, \
-                           n.colmap, n.tm, n.tm_len, n.acc, allow_age, n.stats);               \
+#define DPSNN_DELIVER(FX, WN, UU)                                                              \
+    do {                                                                                       \
+        allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                           \
+        hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(L.n_col), dim3(BS), lds, stream, \
+                           L.descs, L.bmap_col, allow_age);                                    \
     } while (0)
-    if (n.unroll == 1) {
+    if (tune.unroll == 1) {
         if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 1); else DPSNN_DELIVER(true, false, 1); }
         else { if (use_win) DPSNN_DELIVER(false, true, 1); else DPSNN_DELIVER(false, false, 1); }
-    } else if (n.unroll == 2) {
+    } else if (tune.unroll == 2) {
         if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 2); else DPSNN_DELIVER(true, false, 2); }
         else { if (use_win) DPSNN_DELIVER(false, true, 2); else DPSNN_DELIVER(false, false, 2); }
-    } else if (n.unroll == 4) {
+    } else if (tune.unroll == 4) {
         if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 4); else DPSNN_DELIVER(true, false, 4); }
         else { if (use_win) DPSNN_DELIVER(false, true, 4); else DPSNN_DELIVER(false, false, 4); }
     } else {
@@ -875,73 +924,97 @@ hipError_t launch_deliver(Net& n, uint32_t t) {
 
 }  // namespace
 
-// Every kernel of one step, in the paper's loop order.  kind: 0 LTP,
-// 1 delivery, 2 neuron, 3 consolidation (for the per-kernel timers).
-static void mark(Net& n, int kind, bool begin) {
-    if (!n.timing) return;
-    if (begin) {
-        Net::Timed tt;
-        tt.kind = kind;
-        if (n.event_pool.size() >= 2) {
-            tt.a = n.event_pool.back(); n.event_pool.pop_back();
-            tt.b = n.event_pool.back(); n.event_pool.pop_back();
-        } else {
-            (void)hipEventCreate(&tt.a);
-            (void)hipEventCreate(&tt.b);
-        }
-        (void)hipEventRecord(tt.a, n.stream);
-        n.timed.push_back(tt);
+void Timers::begin(int kind, hipStream_t s) {
+    if (!on) return;
+    Timed tt;
+    tt.kind = kind;
+    if (pool.size() >= 2) {
+        tt.a = pool.back(); pool.pop_back();
+        tt.b = pool.back(); pool.pop_back();
     } else {
-        (void)hipEventRecord(n.timed.back().b, n.stream);
+        (void)hipEventCreate(&tt.a);
+        (void)hipEventCreate(&tt.b);
     }
+    (void)hipEventRecord(tt.a, s);
+    pending.push_back(tt);
 }
 
-hipError_t launch_step(Net& n, uint32_t t, uint32_t stim_b, uint32_t stim_e) {
-    const Dims& d = n.d;
+void Timers::end(hipStream_t s) {
+    if (!on) return;
+    (void)hipEventRecord(pending.back().b, s);
+}
+
+void Timers::collect() {
+    for (auto& tt : pending) {
+        float x = 0.0f;
+        if (hipEventElapsedTime(&x, tt.a, tt.b) == hipSuccess) {
+            ms[tt.kind] += x;
+            n[tt.kind] += 1;
+        }
+        pool.push_back(tt.a);
+        pool.push_back(tt.b);
+    }
+    pending.clear();
+}
+
+void Timers::release() {
+    for (auto& tt : pending) {
+        (void)hipEventDestroy(tt.a);
+        (void)hipEventDestroy(tt.b);
+    }
+    pending.clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+}
+
+// One step of every network of the set, in the paper's loop order: LTP,
+// delivery (+ currents and LTD), neuron update, consolidation where due, and
+// the clock tick.  Timer kinds: 0 LTP, 1 delivery, 2 neuron, 3 consolidation.
+hipError_t launch_step_set(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
+                           Net* const* members) {
     hipError_t e;
-    if (t >= 1) {
-        const uint32_t BS = n.ltp_block;
+    bool any_spikes = false;
+    for (uint32_t k = 0; k < L.K; ++k) any_spikes |= members[k]->t >= 1;
+    if (any_spikes) {
+        const uint32_t BS = std::max<uint32_t>(tune.ltp_block, ((L.max_w + 63) / 64) * 64);
         const size_t base = ((size_t)2 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
-        const size_t hw = (size_t)kSlots * d.Ncol * sizeof(uint32_t);
-        const uint32_t allow = (base + hw <= n.max_lds) ? 1u : 0u;
+        const size_t hw = (size_t)kSlots * L.max_ncol * sizeof(uint32_t);
+        const uint32_t allow = (base + hw <= tune.max_lds) ? 1u : 0u;
         const size_t lds = base + (allow ? hw : 0);
         allow_lds(k_ltp<4>, lds);
-        mark(n, 0, true);
-        hipLaunchKernelGGL(k_ltp<4>, dim3(d.C), dim3(BS), lds, n.stream, d, t, n.ring, n.hist,
-                           n.t_old, n.rowptr, n.rev_srcd, n.Pacc, n.srcmap, n.tp, n.tp_len, allow,
-                           n.stats);
-        mark(n, 0, false);
+        tm.begin(0, stream);
+        hipLaunchKernelGGL(k_ltp<4>, dim3(L.n_col), dim3(BS), lds, stream, L.descs, L.bmap_col, allow);
+        tm.end(stream);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        mark(n, 1, true);
-        e = n.tgt16 ? launch_deliver<uint16_t>(n, t) : launch_deliver<uint32_t>(n, t);
-        mark(n, 1, false);
+        tm.begin(1, stream);
+        e = L.tgt16 ? launch_deliver<uint16_t>(L, tune, stream, members)
+                    : launch_deliver<uint32_t>(L, tune, stream, members);
+        tm.end(stream);
         if (e != hipSuccess) return e;
     }
-    const uint32_t words = d.C * d.W;
-    const uint32_t blocks = (words + 3) / 4;
-    mark(n, 2, true);
-#define DPSNN_NEURON(MD)                                                                          \
-    hipLaunchKernelGGL(k_neuron<MD>, dim3(blocks), dim3(256), 0, n.stream, d, t, n.v, n.u, n.acc, \
-                       n.hist, n.t_old, n.t_last, n.ring, n.thal_whole, n.thal_thr,               \
-                       n.cfg.thalamic_current, n.stim_id, n.stim_mv, stim_b, stim_e, n.ev_cnt,    \
-                       n.ev_start, n.ev_key, n.ev_w, n.cursor, n.stats)
-    if (n.cfg.sum_mode == DPSNN_SUM_FIXED) DPSNN_NEURON(DPSNN_SUM_FIXED);
-    else if (n.cfg.sum_mode == DPSNN_SUM_ATOMIC) DPSNN_NEURON(DPSNN_SUM_ATOMIC);
-    else DPSNN_NEURON(DPSNN_SUM_ORDERED);
-#undef DPSNN_NEURON
-    mark(n, 2, false);
+    tm.begin(2, stream);
+    if (L.sum_mode == DPSNN_SUM_FIXED)
+        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_FIXED>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu);
+    else if (L.sum_mode == DPSNN_SUM_ATOMIC)
+        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_ATOMIC>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu);
+    else
+        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_ORDERED>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu);
+    tm.end(stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const uint32_t Tw = n.cfg.weight_update_period;
-    if (Tw && (t + 1) % Tw == 0 && n.S_exc) {
-        const uint64_t blocks_w = std::min<uint64_t>((n.S_exc + 255) / 256, 8192);
-        mark(n, 3, true);
-        hipLaunchKernelGGL(k_wupdate, dim3((uint32_t)blocks_w), dim3(256), 0, n.stream, n.S_exc,
-                           n.rev_fwd, n.Pacc, n.Dacc, n.w, n.cfg.wu_bias, n.cfg.sd_decay,
-                           n.cfg.w_max);
-        mark(n, 3, false);
-        n.consolidations++;
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (uint32_t k = 0; k < L.K; ++k) {
+        Net& n = *members[k];
+        const uint32_t Tw = n.cfg.weight_update_period;
+        if (Tw && (n.t + 1) % Tw == 0 && n.S_exc && L.n_wu[k]) {
+            tm.begin(3, stream);
+            hipLaunchKernelGGL(k_wupdate, dim3(L.n_wu[k]), dim3(256), 0, stream, L.descs + k, L.bmap_wu[k]);
+            tm.end(stream);
+            n.consolidations++;
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(256), 0, stream, L.descs, L.K);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (uint32_t k = 0; k < L.K; ++k) members[k]->t += 1;
     return hipSuccess;
 }
 

@@ -63,7 +63,9 @@ EXPORTS = [
     "dpsnn_default_config", "dpsnn_footprint_bytes", "dpsnn_build_network", "dpsnn_step",
     "dpsnn_sync", "dpsnn_time", "dpsnn_read_spikes", "dpsnn_read_weights",
     "dpsnn_read_connectivity", "dpsnn_read_state", "dpsnn_get_stats", "dpsnn_set_stimulus",
-    "dpsnn_set_timing", "dpsnn_set_tuning", "dpsnn_destroy", "dpsnn_last_error",
+    "dpsnn_set_timing", "dpsnn_set_tuning", "dpsnn_autotune", "dpsnn_destroy",
+    "dpsnn_batch_create", "dpsnn_batch_step", "dpsnn_batch_get_stats", "dpsnn_batch_set_timing",
+    "dpsnn_batch_set_tuning", "dpsnn_batch_autotune", "dpsnn_batch_destroy", "dpsnn_last_error",
 ]
 
 _lib = None
@@ -95,11 +97,20 @@ def lib():
         L.dpsnn_set_stimulus.argtypes = [vp, P(C.c_uint32), P(C.c_uint32), P(C.c_float), C.c_size_t]
         L.dpsnn_set_timing.argtypes = [vp, C.c_int]
         L.dpsnn_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32]
+        L.dpsnn_autotune.argtypes = [vp, C.c_uint32]
         L.dpsnn_destroy.argtypes = [vp]
         L.dpsnn_destroy.restype = None
+        L.dpsnn_batch_create.argtypes = [P(vp), C.c_uint32, P(vp)]
+        L.dpsnn_batch_step.argtypes = [vp, C.c_uint32]
+        L.dpsnn_batch_get_stats.argtypes = [vp, P(dpsnn_stats)]
+        L.dpsnn_batch_set_timing.argtypes = [vp, C.c_int]
+        L.dpsnn_batch_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32]
+        L.dpsnn_batch_autotune.argtypes = [vp, C.c_uint32]
+        L.dpsnn_batch_destroy.argtypes = [vp]
+        L.dpsnn_batch_destroy.restype = None
         L.dpsnn_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("dpsnn_destroy", "dpsnn_last_error"):
+            if name not in ("dpsnn_destroy", "dpsnn_batch_destroy", "dpsnn_last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -272,3 +283,53 @@ class Network:
 
     def set_tuning(self, key: int, value: int):
         _check(lib().dpsnn_set_tuning(self.h, key, value))
+
+    def autotune(self, steps_per_trial: int = 5):
+        _check(lib().dpsnn_autotune(self.h, steps_per_trial))
+
+
+class Batch:
+    """Several networks advanced together with one launch per kernel
+    (dpsnn_batch_create .. dpsnn_batch_destroy).  The networks stay owned by
+    their Network objects; close the batch before closing them."""
+
+    def __init__(self, nets):
+        self.nets = list(nets)
+        arr = (C.c_void_p * len(self.nets))(*[n.h.value for n in self.nets])
+        h = C.c_void_p()
+        _check(lib().dpsnn_batch_create(arr, len(self.nets), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dpsnn_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, n: int = 1):
+        _check(lib().dpsnn_batch_step(self.h, n))
+
+    def stats(self) -> dict:
+        s = dpsnn_stats()
+        _check(lib().dpsnn_batch_get_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in dpsnn_stats._fields_}
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().dpsnn_batch_set_timing(self.h, int(bool(enable))))
+
+    def set_tuning(self, key: int, value: int):
+        _check(lib().dpsnn_batch_set_tuning(self.h, key, value))
+
+    def autotune(self, steps_per_trial: int = 5):
+        _check(lib().dpsnn_batch_autotune(self.h, steps_per_trial))
