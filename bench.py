@@ -92,12 +92,138 @@ def cpu_baseline(cfg, budget_s: float):
     }
 
 
+def _kernel_table(d, bytes_k):
+    kern = {}
+    for k in KERNELS:
+        ms, n = d[f"ms_{k}"], d[f"n_{k}"]
+        if n == 0:
+            continue
+        kern[k] = {"launches": n, "total_ms": round(ms, 3), "avg_us": round(1000 * ms / n, 3),
+                   "algo_bytes_per_launch": bytes_k[k] / n,
+                   "achieved_GBs": round(bytes_k[k] / (ms / 1000.0) / 1e9, 1) if ms > 0 else None}
+    return kern
+
+
+def bench_batched(args, mode):
+    """Many independent networks of uneven size advanced together (one launch
+    per kernel for all of them), against the same networks stepped one at a
+    time.  Both sets start from t = 0 and are timed over the same steps."""
+    import torch
+    from paper_1310_8478_amd import dpsnn as dp
+    from paper_1310_8478_amd import workloads as W
+
+    cfgs = [dict(c, sum_mode=mode) for c in W.batched_mix(args.nets)]
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    nets = [dp.Network(c, device=0) for c in cfgs]
+    build_s = time.perf_counter() - t0
+    N = sum(n.N for n in nets)
+    S = sum(n.N * n.M for n in nets)
+    print(f"[bench] built {len(nets)} networks ({N} neurons, {S} synapses) in {build_s:.2f} s",
+          file=sys.stderr, flush=True)
+    batch = dp.Batch(nets)
+    tune_steps = 0
+    if args.warmup >= 36:
+        batch.autotune(steps_per_trial=3)       # 2 rounds x 6 shapes x 3 steps
+        tune_steps = 36
+    if args.warmup > tune_steps:
+        batch.step(args.warmup - tune_steps)
+    batch.set_timing(True)
+    s0 = batch.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.steps:
+        k = min(100, args.steps - done)
+        batch.step(k)
+        done += k
+        if done % 500 == 0 or done == args.steps:
+            torch.cuda.synchronize()
+            print(f"[bench] batched {done}/{args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s1 = batch.stats()
+    batch.close()
+    for n in nets:
+        n.close()
+    d = {k: s1[k] - s0[k] for k in s1 if isinstance(s1[k], (int, float))}
+
+    # the same networks, stepped one network at a time
+    seq = [dp.Network(c, device=0) for c in cfgs]
+    for n in seq:
+        n.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = sum(n.stats()["events"] for n in seq)
+    t0 = time.perf_counter()
+    for step in range(args.steps):
+        for n in seq:
+            n.step(1)
+        if (step + 1) % 500 == 0:
+            torch.cuda.synchronize()
+            print(f"[bench] one-by-one {step + 1}/{args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall_seq = time.perf_counter() - t0
+    e1 = sum(n.stats()["events"] for n in seq)
+    for n in seq:
+        n.close()
+
+    exc_ev = d["events_exc"]
+    inh_ev = d["events"] - exc_ev
+    Nexc_syn = sum(int(c["grid_x"] * c["grid_y"] * round(c["exc_fraction"] * c["neurons_per_column"])
+                       * c["synapses_per_neuron"]) for c in cfgs)
+    bytes_k = {
+        "deliver": exc_ev * BYTES_EXC_EVENT_U16 + inh_ev * BYTES_INH_EVENT_U16,
+        "ltp": d["ltp_visits"] * BYTES_LTP_VISIT,
+        "neuron": d["n_neuron"] * N * BYTES_NEURON,
+        "wupdate": Nexc_syn * BYTES_CONSOLIDATION * (d["n_wupdate"] / max(1, len(cfgs))),
+    }
+    kern = _kernel_table(d, bytes_k)
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    ach = kern[dom]["achieved_GBs"]
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": None,
+            "kernel": f"k_{dom}", "avg_launch_us": kern[dom]["avg_us"],
+            "algo_bytes_per_launch": kern[dom]["algo_bytes_per_launch"]}
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfgs[0], args.cpu_seconds)
+    sides = sorted(c["grid_x"] for c in cfgs)
+    rate_hz = d["spikes"] / N / (args.steps / 1000.0)
+    out = {
+        "metric": "synaptic events/s",
+        "value": d["events"] / wall,
+        "unit": "events/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * wall / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if mode != W.SUM_FIXED else "f32+i64acc",
+        "data": "synthetic (seeded Philox networks and thalamic input, as in the paper)",
+        "config": {
+            "workload": (f"batched: {len(cfgs)} independent networks, square grids of side "
+                         f"{sides[0]}..{sides[-1]} x 1250 neurons, M 100-400, thalamic 0.5-2/column/ms, "
+                         f"seeds 2000+b, one launch per kernel for all networks, autotuned shapes"),
+            "neurons": N, "synapses": S, "sum_mode": args.mode,
+            "timed_steps": f"{args.warmup}..{args.warmup + args.steps - 1}",
+        },
+        "one_by_one_events_per_s": (e1 - e0) / wall_seq,
+        "batch_speedup": (d["events"] / wall) / ((e1 - e0) / wall_seq) if e1 > e0 else None,
+        "rate_hz": rate_hz,
+        "build_s": build_s,
+        "kernels": kern,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large"])
+    ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large", "batched"])
+    ap.add_argument("--nets", type=int, default=32, help="networks in the batched workload")
     ap.add_argument("--mode", default="fixed", choices=["fixed", "atomic", "ordered"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -127,6 +253,8 @@ def main():
     from paper_1310_8478_amd import workloads as W
 
     mode = {"fixed": W.SUM_FIXED, "atomic": W.SUM_ATOMIC, "ordered": W.SUM_ORDERED}[args.mode]
+    if args.workload == "batched":
+        return bench_batched(args, mode)
     make, _ = W.WORKLOADS[args.workload]
     cfg = make(sum_mode=mode)
     torch.cuda.set_device(0)
