@@ -217,13 +217,138 @@ def bench_batched(args, mode):
     print(json.dumps(out))
 
 
+def bench_serving(args, mode):
+    """Continuous-batching serving: a Poisson stream of jobs (uneven networks,
+    100-2000 steps each) submitted at their arrival times to a job server that
+    admits them by device footprint and steps every admitted job together.
+    Latency = result readable (last step completed) - submission, build
+    included.  Throughput = events of all jobs / (last completion - first
+    submission)."""
+    import threading
+
+    import numpy as np
+    import torch
+    from paper_1310_8478_amd import dpsnn as dp
+    from paper_1310_8478_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    reqs = W.serving_stream(args.requests, lam=args.rate)
+    for r in reqs:
+        r["config"] = dict(r["config"], sum_mode=mode)
+    srv = dp.Server(device=0, budget_bytes=int(args.budget_gb * 1e9), max_quantum=args.quantum)
+    # warm-up jobs (not timed): load the kernels and fill the allocator's cache
+    warm = [srv.submit(W.make_config(grid_x=4, grid_y=4, synapses_per_neuron=300, sum_mode=mode,
+                                     seed=9000 + k), 50) for k in range(max(0, args.warmup_jobs))]
+    for j in warm:
+        srv.wait(j)
+        srv.release(j)
+    while srv.wait_any(timeout=0.0) is not None:
+        pass
+
+    done = []
+    lock = threading.Lock()
+    errors = []
+
+    def consume():
+        n = 0
+        while n < len(reqs):
+            info = srv.wait_any(timeout=600.0)
+            if info is None:
+                errors.append("no job finished within 600 s")
+                return
+            n += 1
+            if info["status"] != dp.JOB_DONE:
+                errors.append(f"job {info['id']} failed: {info['message']}")
+                srv.release(info["id"])
+                continue
+            net = srv.job_network(info["id"])
+            ev = net.stats()["events"]
+            spikes = net.stats()["spikes"]
+            srv.release(info["id"])
+            with lock:
+                done.append(dict(info, events=ev, spikes=spikes, net=None))
+            if n % 25 == 0 or n == len(reqs):
+                print(f"[bench] serving: {n}/{len(reqs)} jobs done", file=sys.stderr, flush=True)
+
+    th = threading.Thread(target=consume)
+    th.start()
+    start = time.perf_counter()
+    lag = 0.0
+    for r in reqs:
+        delay = r["arrival"] - (time.perf_counter() - start)
+        if delay > 0:
+            time.sleep(delay)
+        lag = max(lag, (time.perf_counter() - start) - r["arrival"])
+        srv.submit(r["config"], r["steps"])
+    th.join()
+    st = srv.stats()
+    srv.close()
+    if errors:
+        raise RuntimeError("; ".join(errors[:5]))
+
+    if args.jobs_out:
+        with open(args.jobs_out, "w") as f:
+            json.dump([dict(d, grid=reqs[d["id"] - len(warm) - 1]["config"]["grid_x"],
+                            M=reqs[d["id"] - len(warm) - 1]["config"]["synapses_per_neuron"])
+                       for d in done], f)
+    lat = np.array([d["t_done"] - d["t_submit"] for d in done])
+    queue_s = np.array([d["t_admit"] - d["t_submit"] for d in done])
+    build = np.array([d["t_built"] - d["t_admit"] for d in done])
+    first = min(d["t_submit"] for d in done)
+    last = max(d["t_done"] for d in done)
+    span = last - first
+    events = sum(d["events"] for d in done)
+    job_steps = sum(r["steps"] for r in reqs)
+    syn = [r["config"]["grid_x"] * r["config"]["grid_y"] * r["config"]["neurons_per_column"]
+           * r["config"]["synapses_per_neuron"] for r in reqs]
+    out = {
+        "metric": "synaptic events/s",
+        "value": events / span,
+        "unit": "events/s",
+        "n_gpus": 1, "steps": job_steps, "warmup": len(warm),
+        "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if mode != W.SUM_FIXED else "f32+i64acc",
+        "data": "synthetic (seeded Philox networks and thalamic input, as in the paper)",
+        "config": {
+            "workload": (f"serving: {len(reqs)} jobs, Poisson arrivals at {args.rate}/s, square grids "
+                         f"of side 4..32 x 1250 neurons, M 100-625, 100-2000 steps, seeds 3000+k, "
+                         f"admission by footprint within {args.budget_gb:g} GB"),
+            "sum_mode": args.mode, "max_quantum": args.quantum,
+            "synapses_per_job_mean": float(np.mean(syn)),
+        },
+        "serve_p50_s": float(np.percentile(lat, 50)),
+        "serve_p99_s": float(np.percentile(lat, 99)),
+        "serve_max_s": float(lat.max()),
+        "queue_wait_mean_s": float(queue_s.mean()),
+        "build_mean_s": float(build.mean()),
+        "jobs_per_s": len(done) / span,
+        "span_s": span,
+        "submit_lag_max_s": lag,
+        "arrivals_span_s": reqs[-1]["arrival"],
+        "peak_running": st["peak_running"],
+        "peak_reserved_GB": st["peak_reserved_bytes"] / 1e9,
+        "quanta": st["quanta"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="large", choices=["tiny", "mid", "large", "batched"])
+    ap.add_argument("--workload", default="large",
+                    choices=["tiny", "mid", "large", "batched", "serving"])
     ap.add_argument("--nets", type=int, default=32, help="networks in the batched workload")
+    ap.add_argument("--requests", type=int, default=400, help="jobs in the serving workload")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving arrivals per second")
+    ap.add_argument("--budget-gb", type=float, default=240.0, help="serving admission budget")
+    ap.add_argument("--quantum", type=int, default=8, help="serving steps per quantum")
+    ap.add_argument("--warmup-jobs", type=int, default=4)
+    ap.add_argument("--jobs-out", default="", help="serving: write per-job records (JSON) here")
     ap.add_argument("--mode", default="fixed", choices=["fixed", "atomic", "ordered"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -255,6 +380,8 @@ def main():
     mode = {"fixed": W.SUM_FIXED, "atomic": W.SUM_ATOMIC, "ordered": W.SUM_ORDERED}[args.mode]
     if args.workload == "batched":
         return bench_batched(args, mode)
+    if args.workload == "serving":
+        return bench_serving(args, mode)
     make, _ = W.WORKLOADS[args.workload]
     cfg = make(sum_mode=mode)
     torch.cuda.set_device(0)

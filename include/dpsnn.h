@@ -45,6 +45,7 @@ extern "C" {
 #define DPSNN_E_DEVICE (-3)   /* a HIP runtime call failed */
 #define DPSNN_E_RANGE  (-4)   /* requested steps are not (or no longer) held */
 #define DPSNN_E_BUFSZ  (-5)   /* caller buffer too small; *n_out holds the size needed */
+#define DPSNN_E_TIMEOUT (-6)  /* a wait ended before the job finished */
 
 /* Current summation modes (the paper fixes no order or precision for the
  * sum of currents arriving in one step; Sec. 2, "Projection of synapses"). */
@@ -203,6 +204,93 @@ int dpsnn_batch_autotune(dpsnn_batch *batch, uint32_t steps_per_trial);
 /* Releases the batch's tables; the member networks stay valid and can be
  * stepped alone again. */
 void dpsnn_batch_destroy(dpsnn_batch *batch);
+
+/* ---- Serving: a continuous-batching job server -------------------------
+ * A job is a network configuration plus a number of steps; its result is the
+ * network after those steps, exactly as dpsnn_build_network + dpsnn_step
+ * would leave it (every draw is keyed by the job's seed and global ids).
+ * A server runs jobs on one device with two threads of its own:
+ *   - the builder admits queued jobs strictly in submission order while the
+ *     admitted jobs' footprints (dpsnn_footprint_bytes) fit the byte budget
+ *     and fewer than max_jobs are admitted, and generates each job's network
+ *     on the server's build stream;
+ *   - the stepper advances every built job on the server's step stream in
+ *     quanta of at most max_quantum steps (a quantum also ends where the
+ *     first running job finishes): jobs sharing the summation mode and the
+ *     target-index width step together with one launch per kernel, each
+ *     DPSNN_SUM_ORDERED job alone.  Built jobs join, and finished jobs leave,
+ *     between quanta; the host stays at most one quantum ahead of the device.
+ * A job is DONE when its last step has completed on the device.  Its network
+ * then stays on the device, owned by the server, for the read_* calls and
+ * dpsnn_get_stats (which use the server's read stream; dpsnn_step also works
+ * on it), and its footprint stays reserved until dpsnn_server_release.
+ * dpsnn_destroy refuses such a network.
+ * The device's alloc/free callbacks (thread-safe; called from the server's
+ * threads and from dpsnn_server_release) serve every device allocation of the
+ * jobs; without callbacks the server allocates with hipMallocAsync and frees
+ * with hipFreeAsync on its own streams.  Its stream field is ignored.
+ * All entry points may be called from any host thread. */
+typedef struct dpsnn_server dpsnn_server;
+
+#define DPSNN_JOB_QUEUED  0   /* submitted, not admitted yet */
+#define DPSNN_JOB_RUNNING 1   /* admitted: being built or stepped */
+#define DPSNN_JOB_DONE    2   /* all steps completed; results readable */
+#define DPSNN_JOB_FAILED  3   /* build or step failed, or the server shut down */
+
+typedef struct dpsnn_job_info {
+    uint64_t   id;
+    int32_t    status;           /* DPSNN_JOB_* */
+    int32_t    error;            /* DPSNN_E_* code when FAILED, else 0 */
+    uint32_t   steps;            /* steps requested */
+    uint32_t   steps_launched;   /* steps enqueued on the device so far */
+    uint64_t   footprint;        /* device bytes reserved for the job */
+    /* seconds on the server clock (dpsnn_server_clock); 0 = not reached */
+    double     t_submit, t_admit, t_built, t_done;
+    dpsnn_net *net;              /* the job's network once DONE, else NULL */
+    char       message[160];     /* failure message when FAILED */
+} dpsnn_job_info;
+
+typedef struct dpsnn_server_stats {
+    uint64_t submitted, completed, failed, released;
+    uint64_t queued, running;        /* jobs in each state now */
+    uint64_t quanta;                 /* quanta launched by the stepper */
+    uint64_t set_steps;              /* launches of one step over one job group */
+    uint64_t job_steps;              /* steps launched, summed over jobs */
+    uint64_t budget_bytes, reserved_bytes, peak_reserved_bytes;
+    uint64_t peak_running;           /* most jobs admitted at once */
+} dpsnn_server_stats;
+
+/* budget_bytes = 0 takes 90 % of the device memory free at creation.
+ * max_quantum: steps per quantum (0 = 8).  max_jobs: jobs admitted at once
+ * (0 = 256). */
+int dpsnn_server_create(const dpsnn_device *dev, uint64_t budget_bytes, uint32_t max_quantum,
+                        uint32_t max_jobs, dpsnn_server **out);
+/* Queue a job of `steps` steps (1 .. 2^20 - 1).  If cfg->raster_steps is 0
+ * the job keeps the raster of its whole run (raster_steps = steps + 1).
+ * DPSNN_E_INVAL for an invalid configuration, DPSNN_E_NOMEM if its footprint
+ * exceeds the whole budget.  Never blocks on device work. */
+int dpsnn_server_submit(dpsnn_server *srv, const dpsnn_config *cfg, uint32_t steps,
+                        uint64_t *job);
+/* Current state of a job; DPSNN_E_INVAL for an unknown or released id. */
+int dpsnn_server_query(dpsnn_server *srv, uint64_t job, dpsnn_job_info *info);
+/* Block until the job is DONE or FAILED (timeout_s < 0: no limit), then
+ * fill *info.  DPSNN_E_TIMEOUT (with *info filled) if the time ran out. */
+int dpsnn_server_wait(dpsnn_server *srv, uint64_t job, double timeout_s, dpsnn_job_info *info);
+/* Block until some job finishes that no earlier dpsnn_server_wait_any call
+ * returned; jobs are returned in the order they finished.
+ * DPSNN_E_TIMEOUT if none finished in time. */
+int dpsnn_server_wait_any(dpsnn_server *srv, double timeout_s, dpsnn_job_info *info);
+/* Free a DONE or FAILED job's network and return its footprint to the
+ * budget.  DPSNN_E_INVAL if the job is still queued or running, or if its
+ * network belongs to a batch. */
+int dpsnn_server_release(dpsnn_server *srv, uint64_t job);
+int dpsnn_server_get_stats(dpsnn_server *srv, dpsnn_server_stats *stats);
+/* Seconds since the server was created (steady clock). */
+int dpsnn_server_clock(dpsnn_server *srv, double *seconds);
+/* Stop both threads after the quanta already launched, mark jobs that were
+ * still queued or running FAILED, and free every job's network.  No other
+ * call on the server may be in progress or follow. */
+void dpsnn_server_destroy(dpsnn_server *srv);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *dpsnn_last_error(void);

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libdpsnn.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["build.hip", "step.hip", "read.hip", "api.cpp"]
+SOURCES = ["build.hip", "step.hip", "read.hip", "api.cpp", "serve.cpp"]
 
 # -ffp-contract=off: the neuron and STDP expressions must round after every
 # operation, as the reference semantics do.  Packed fp32 instructions are kept
@@ -54,7 +54,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(one, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"linking libdpsnn.so failed:\n{r.stdout}\n{r.stderr}")

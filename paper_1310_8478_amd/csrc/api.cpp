@@ -15,14 +15,20 @@
 
 using namespace dpsnn;
 
-namespace {
+namespace dpsnn {
 
+namespace {
 thread_local std::string g_err;
+}
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
+
+}  // namespace dpsnn
+
+namespace {
 
 #define DPSNN_HIP(expr)                                                                 \
     do {                                                                                \
@@ -212,6 +218,12 @@ int upload(Net& n, T* dst, const std::vector<T>& src) {
     return DPSNN_OK;
 }
 
+}  // namespace
+
+namespace dpsnn {
+
+void destroy_net(Net* n) { release(n); }
+
 // Device allocation through a dpsnn_device (callbacks or hipMalloc), recorded
 // in `track` so that its owner frees it.
 void* dev_alloc(const dpsnn_device& dev, hipStream_t stream, size_t bytes,
@@ -227,18 +239,32 @@ void* dev_alloc(const dpsnn_device& dev, hipStream_t stream, size_t bytes,
     return p;
 }
 
-// Descriptor tables and block maps of a launch over `cnt` networks.
+void free_tracked(const dpsnn_device& dev, hipStream_t stream, std::vector<Net::Alloc>& allocs) {
+    for (auto& a : allocs) {
+        if (dev.free) dev.free(a.p, a.bytes, stream, dev.ctx);
+        else (void)hipFree(a.p);
+    }
+    allocs.clear();
+}
+
+// Descriptor tables and block maps of a launch over `cnt` networks.  The host
+// copies stay in L, so with sync == false the uploads may still be in flight
+// on `stream` when this returns (L must then outlive them).
 int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_device& dev,
-                    hipStream_t stream, std::vector<Net::Alloc>* track) {
+                    hipStream_t stream, std::vector<Net::Alloc>* track, bool sync) {
     L.K = cnt;
     L.max_ncol = 0;
     L.max_w = 0;
     L.sum_mode = m[0]->cfg.sum_mode;
     L.tgt16 = m[0]->tgt16;
-    std::vector<uint2> col, neu;
+    std::vector<uint2>& col = L.host_col;
+    std::vector<uint2>& neu = L.host_neu;
+    col.clear();
+    neu.clear();
     L.bmap_wu.assign(cnt, nullptr);
     L.n_wu.assign(cnt, 0);
-    std::vector<std::vector<uint2>> wu(cnt);
+    std::vector<std::vector<uint2>>& wu = L.host_wu;
+    wu.assign(cnt, {});
     const uint64_t wchunk = 256ull * kWupdateItems;
     for (uint32_t k = 0; k < cnt; ++k) {
         const Dims& d = m[k]->d;
@@ -269,9 +295,13 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
     L.host_descs.resize(cnt);
     for (uint32_t k = 0; k < cnt; ++k) L.host_descs[k] = m[k]->make_desc();
     DPSNN_HIP(hipMemcpyAsync(L.descs, L.host_descs.data(), sizeof(NetDesc) * cnt, hipMemcpyHostToDevice, stream));
-    DPSNN_HIP(hipStreamSynchronize(stream));
+    if (sync) DPSNN_HIP(hipStreamSynchronize(stream));
     return DPSNN_OK;
 }
+
+}  // namespace dpsnn
+
+namespace {
 
 int refresh_descs(LaunchSet& L, Net* const* m, hipStream_t stream) {
     for (uint32_t k = 0; k < L.K; ++k) L.host_descs[k] = m[k]->make_desc();
@@ -561,7 +591,7 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     }
     {
         Net* one[1] = {n};
-        DPSNN_TRY(make_launch_set(n->solo, one, 1, n->dev, n->stream, &n->allocs));
+        DPSNN_TRY(make_launch_set(n->solo, one, 1, n->dev, n->stream, &n->allocs, true));
     }
 #undef DPSNN_TRY
 #undef DPSNN_TRY_HIP
@@ -843,6 +873,10 @@ void dpsnn_destroy(dpsnn_net* h) {
         fail(DPSNN_E_INVAL, "destroying a network that belongs to a batch");
         return;
     }
+    if (n && n->owner) {
+        fail(DPSNN_E_INVAL, "a server job's network is freed by dpsnn_server_release");
+        return;
+    }
     release(n);
 }
 
@@ -870,11 +904,9 @@ int dpsnn_batch_create(dpsnn_net* const* nets, uint32_t n_nets, dpsnn_batch** ou
     b->stream = m[0]->stream;
     b->dev = m[0]->dev;
     b->tune = m[0]->tune;
-    int rc = make_launch_set(b->L, b->members.data(), n_nets, b->dev, b->stream, &b->allocs);
+    int rc = make_launch_set(b->L, b->members.data(), n_nets, b->dev, b->stream, &b->allocs, true);
     if (rc) {
-        for (auto& a : b->allocs) {
-            if (b->dev.free) b->dev.free(a.p, a.bytes, b->stream, b->dev.ctx); else (void)hipFree(a.p);
-        }
+        free_tracked(b->dev, b->stream, b->allocs);
         delete b;
         return rc;
     }
@@ -887,9 +919,9 @@ int dpsnn_batch_step(dpsnn_batch* b, uint32_t n_steps) {
     if (!b) return fail(DPSNN_E_INVAL, "batch is NULL");
     for (Net* x : b->members)
         if ((uint64_t)x->t + n_steps >= (1ull << 31)) return fail(DPSNN_E_RANGE, "step count overflow");
+    // members' descriptors cannot change while they are in the batch (their
+    // stimulus is fixed), so the tables uploaded at creation stay valid
     DPSNN_HIP(hipSetDevice(b->dev.device));
-    int rc = refresh_descs(b->L, b->members.data(), b->stream);
-    if (rc) return rc;
     for (uint32_t s = 0; s < n_steps; ++s)
         DPSNN_HIP(launch_step_set(b->L, b->tune, b->timers, b->stream, b->members.data()));
     return DPSNN_OK;
@@ -931,8 +963,6 @@ int dpsnn_batch_set_tuning(dpsnn_batch* b, uint32_t key, uint32_t value) {
 int dpsnn_batch_autotune(dpsnn_batch* b, uint32_t steps_per_trial) {
     if (!b) return fail(DPSNN_E_INVAL, "batch is NULL");
     DPSNN_HIP(hipSetDevice(b->dev.device));
-    int rc = refresh_descs(b->L, b->members.data(), b->stream);
-    if (rc) return rc;
     return autotune(b->L, b->tune, b->timers, b->stream, b->members.data(), steps_per_trial);
 }
 
@@ -940,9 +970,7 @@ void dpsnn_batch_destroy(dpsnn_batch* b) {
     if (!b) return;
     (void)hipSetDevice(b->dev.device);
     (void)hipStreamSynchronize(b->stream);
-    for (auto& a : b->allocs) {
-        if (b->dev.free) b->dev.free(a.p, a.bytes, b->stream, b->dev.ctx); else (void)hipFree(a.p);
-    }
+    free_tracked(b->dev, b->stream, b->allocs);
     b->timers.release();
     for (Net* x : b->members) x->in_batch = false;
     delete b;

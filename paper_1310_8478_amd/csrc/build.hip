@@ -164,16 +164,16 @@ __global__ __launch_bounds__(1024) void k_scan_add(uint32_t* __restrict__ out,
 
 }  // namespace
 
-// out[0..count) = exclusive prefix of in, out[count] = total.
-hipError_t scan_u32(Net& n, const uint32_t* in, uint32_t* out, uint32_t count) {
+// out[0..count) = exclusive prefix of in, out[count] = total, on `stream`.
+hipError_t scan_u32(Net& n, hipStream_t stream, const uint32_t* in, uint32_t* out, uint32_t count) {
     const uint32_t bs = 1024;
     const uint32_t nb = (count + bs - 1) / bs;
     if (nb == 0) {
-        return hipMemsetAsync(out, 0, sizeof(uint32_t), n.stream);
+        return hipMemsetAsync(out, 0, sizeof(uint32_t), stream);
     }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(bs), 0, n.stream, in, out, n.scan_tmp, count);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(bs), 0, n.stream, n.scan_tmp, nb, out, count);
-    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(bs), 0, n.stream, out, n.scan_tmp, count);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(bs), 0, stream, in, out, n.scan_tmp, count);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(bs), 0, stream, n.scan_tmp, nb, out, count);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(bs), 0, stream, out, n.scan_tmp, count);
     return hipGetLastError();
 }
 
@@ -186,7 +186,7 @@ hipError_t launch_build(Net& n) {
     hipLaunchKernelGGL(k_count_rows, dim3(gb), dim3(256), 0, n.stream, d, n.colmap, n.seg_off,
                        n.cursor);
     hipLaunchKernelGGL(k_col_scan, dim3(d.C), dim3(1024), 0, n.stream, d, n.seg_off);
-    if ((e = scan_u32(n, n.cursor, n.rowptr, d.N)) != hipSuccess) return e;
+    if ((e = scan_u32(n, n.stream, n.cursor, n.rowptr, d.N)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(n.cursor, 0, sizeof(uint32_t) * d.N, n.stream)) != hipSuccess) return e;
     // every entry is written below; zeroing keeps stray reads in bounds if not
     if ((e = hipMemsetAsync(n.tgt, 0, (n.tgt16 ? 2 : 4) * (size_t)n.S, n.stream)) != hipSuccess) return e;

@@ -47,7 +47,10 @@ struct LaunchSet {
     std::vector<uint32_t> n_wu;
     uint32_t max_ncol = 0, max_w = 0, sum_mode = 0;
     bool tgt16 = true;
+    // host copies of the uploaded tables
     std::vector<NetDesc> host_descs;
+    std::vector<uint2> host_col, host_neu;
+    std::vector<std::vector<uint2>> host_wu;
 };
 
 // Device arrays of one network.  Layout (all device memory):
@@ -70,6 +73,7 @@ struct Net {
     uint32_t t = 0;                // host mirror of the device clock
     bool tgt16 = true;
     bool in_batch = false;
+    void* owner = nullptr;         // the job server holding this network, if any
     uint64_t S = 0, S_exc = 0;
 
     // allocations
@@ -124,6 +128,17 @@ struct Net {
     NetDesc make_desc() const;
 };
 
+// Host helpers shared by the C ABI files (api.cpp, serve.cpp).
+// Records msg as the calling thread's last error and returns code.
+int fail(int code, const std::string& msg);
+void* dev_alloc(const dpsnn_device& dev, hipStream_t stream, size_t bytes,
+                std::vector<Net::Alloc>* track);
+void free_tracked(const dpsnn_device& dev, hipStream_t stream, std::vector<Net::Alloc>& allocs);
+int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_device& dev,
+                    hipStream_t stream, std::vector<Net::Alloc>* track, bool sync);
+// Frees every device allocation of n (after synchronising its stream) and n.
+void destroy_net(Net* n);
+
 // launchers (return hipError_t)
 hipError_t launch_build(Net& n);
 // One step of every network of the set; members[k] is the network of slot k.
@@ -132,6 +147,6 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune, Timers& tm, hipStre
 hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, float* Pf, uint32_t* tgt_out,
                             uint8_t* dly_out, float* w_out, float* P_out, float* D_out);
 hipError_t launch_scatter_P(Net& n, float* Pf);
-hipError_t scan_u32(Net& n, const uint32_t* in, uint32_t* out, uint32_t count);
+hipError_t scan_u32(Net& n, hipStream_t stream, const uint32_t* in, uint32_t* out, uint32_t count);
 
 }  // namespace dpsnn

@@ -882,7 +882,7 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
         hipLaunchKernelGGL((k_deliver_seq<0, TgtT>), dim3(L.n_col), dim3(256), 0, stream, L.descs,
                            L.bmap_col);
         if (n.t >= 1) {
-            hipError_t e = scan_u32(n, n.ev_cnt, n.ev_start, n.d.N);
+            hipError_t e = scan_u32(n, stream, n.ev_cnt, n.ev_start, n.d.N);
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL((k_deliver_seq<1, TgtT>), dim3(L.n_col), dim3(256), 0, stream, L.descs,

@@ -15,7 +15,8 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdpsnn.so")
 
-E_INVAL, E_NOMEM, E_DEVICE, E_RANGE, E_BUFSZ = -1, -2, -3, -4, -5
+E_INVAL, E_NOMEM, E_DEVICE, E_RANGE, E_BUFSZ, E_TIMEOUT = -1, -2, -3, -4, -5, -6
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 SUM_ORDERED, SUM_ATOMIC, SUM_FIXED = 0, 1, 2
 
 
@@ -59,14 +60,37 @@ class dpsnn_stats(C.Structure):
     ]
 
 
+class dpsnn_job_info(C.Structure):
+    _fields_ = [
+        ("id", C.c_uint64), ("status", C.c_int32), ("error", C.c_int32), ("steps", C.c_uint32),
+        ("steps_launched", C.c_uint32), ("footprint", C.c_uint64), ("t_submit", C.c_double),
+        ("t_admit", C.c_double), ("t_built", C.c_double), ("t_done", C.c_double),
+        ("net", C.c_void_p), ("message", C.c_char * 160),
+    ]
+
+
+class dpsnn_server_stats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+        ("released", C.c_uint64), ("queued", C.c_uint64), ("running", C.c_uint64),
+        ("quanta", C.c_uint64), ("set_steps", C.c_uint64), ("job_steps", C.c_uint64),
+        ("budget_bytes", C.c_uint64), ("reserved_bytes", C.c_uint64),
+        ("peak_reserved_bytes", C.c_uint64), ("peak_running", C.c_uint64),
+    ]
+
+
 EXPORTS = [
     "dpsnn_default_config", "dpsnn_footprint_bytes", "dpsnn_build_network", "dpsnn_step",
     "dpsnn_sync", "dpsnn_time", "dpsnn_read_spikes", "dpsnn_read_weights",
     "dpsnn_read_connectivity", "dpsnn_read_state", "dpsnn_get_stats", "dpsnn_set_stimulus",
     "dpsnn_set_timing", "dpsnn_set_tuning", "dpsnn_autotune", "dpsnn_destroy",
     "dpsnn_batch_create", "dpsnn_batch_step", "dpsnn_batch_get_stats", "dpsnn_batch_set_timing",
-    "dpsnn_batch_set_tuning", "dpsnn_batch_autotune", "dpsnn_batch_destroy", "dpsnn_last_error",
+    "dpsnn_batch_set_tuning", "dpsnn_batch_autotune", "dpsnn_batch_destroy",
+    "dpsnn_server_create", "dpsnn_server_submit", "dpsnn_server_query", "dpsnn_server_wait",
+    "dpsnn_server_wait_any", "dpsnn_server_release", "dpsnn_server_get_stats", "dpsnn_server_clock",
+    "dpsnn_server_destroy", "dpsnn_last_error",
 ]
+_VOID = ("dpsnn_destroy", "dpsnn_batch_destroy", "dpsnn_server_destroy", "dpsnn_last_error")
 
 _lib = None
 
@@ -108,9 +132,20 @@ def lib():
         L.dpsnn_batch_autotune.argtypes = [vp, C.c_uint32]
         L.dpsnn_batch_destroy.argtypes = [vp]
         L.dpsnn_batch_destroy.restype = None
+        L.dpsnn_server_create.argtypes = [P(dpsnn_device), C.c_uint64, C.c_uint32, C.c_uint32,
+                                          P(vp)]
+        L.dpsnn_server_submit.argtypes = [vp, P(dpsnn_config), C.c_uint32, P(C.c_uint64)]
+        L.dpsnn_server_query.argtypes = [vp, C.c_uint64, P(dpsnn_job_info)]
+        L.dpsnn_server_wait.argtypes = [vp, C.c_uint64, C.c_double, P(dpsnn_job_info)]
+        L.dpsnn_server_wait_any.argtypes = [vp, C.c_double, P(dpsnn_job_info)]
+        L.dpsnn_server_release.argtypes = [vp, C.c_uint64]
+        L.dpsnn_server_get_stats.argtypes = [vp, P(dpsnn_server_stats)]
+        L.dpsnn_server_clock.argtypes = [vp, P(C.c_double)]
+        L.dpsnn_server_destroy.argtypes = [vp]
+        L.dpsnn_server_destroy.restype = None
         L.dpsnn_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("dpsnn_destroy", "dpsnn_batch_destroy", "dpsnn_last_error"):
+            if name not in _VOID:
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -195,9 +230,25 @@ class Network:
         self.N = self._c.grid_x * self._c.grid_y * self.Ncol
         self.M = self._c.synapses_per_neuron
 
+    @classmethod
+    def _view(cls, handle: int, cfg: dict):
+        """A Network object over a handle owned elsewhere (a server job);
+        close() only forgets the handle."""
+        self = cls.__new__(cls)
+        self.cfg = dict(cfg)
+        self._c = to_config(cfg)
+        self._allocator = None
+        self._owned = False
+        self.h = C.c_void_p(handle)
+        self.Ncol = self._c.neurons_per_column
+        self.N = self._c.grid_x * self._c.grid_y * self.Ncol
+        self.M = self._c.synapses_per_neuron
+        return self
+
     def close(self):
         if getattr(self, "h", None):
-            lib().dpsnn_destroy(self.h)
+            if getattr(self, "_owned", True):
+                lib().dpsnn_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -333,3 +384,103 @@ class Batch:
 
     def autotune(self, steps_per_trial: int = 5):
         _check(lib().dpsnn_batch_autotune(self.h, steps_per_trial))
+
+
+def _info(x: dpsnn_job_info) -> dict:
+    return dict(id=x.id, status=x.status, error=x.error, steps=x.steps,
+                steps_launched=x.steps_launched, footprint=x.footprint, t_submit=x.t_submit,
+                t_admit=x.t_admit, t_built=x.t_built, t_done=x.t_done, net=x.net,
+                message=x.message.decode(errors="replace"))
+
+
+class Server:
+    """Continuous-batching job server (dpsnn_server_create .. _destroy): jobs
+    are admitted by device footprint against `budget_bytes`, generated on the
+    server's build stream and stepped together; a finished job's network stays
+    readable through job_network() until release()."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, max_quantum: int = 0,
+                 max_jobs: int = 0, torch_alloc: bool = True):
+        self._allocator = None
+        dev = dpsnn_device()
+        dev.device = device
+        dev.stream = None
+        if torch_alloc:
+            import torch
+            torch.cuda.set_device(device)
+            self._allocator = _TorchAllocator(device)
+            dev.alloc = self._allocator.alloc
+            dev.free = self._allocator.free
+        dev.ctx = None
+        self._dev = dev
+        self._cfgs = {}
+        h = C.c_void_p()
+        _check(lib().dpsnn_server_create(C.byref(dev), budget_bytes, max_quantum, max_jobs,
+                                         C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dpsnn_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, cfg: dict, steps: int) -> int:
+        c = to_config(cfg)
+        j = C.c_uint64()
+        _check(lib().dpsnn_server_submit(self.h, C.byref(c), steps, C.byref(j)))
+        self._cfgs[j.value] = dict(cfg)
+        return j.value
+
+    def query(self, job: int) -> dict:
+        x = dpsnn_job_info()
+        _check(lib().dpsnn_server_query(self.h, job, C.byref(x)))
+        return _info(x)
+
+    def wait(self, job: int, timeout: float | None = None) -> dict:
+        x = dpsnn_job_info()
+        _check(lib().dpsnn_server_wait(self.h, job, -1.0 if timeout is None else timeout,
+                                       C.byref(x)))
+        return _info(x)
+
+    def wait_any(self, timeout: float | None = None):
+        """The next finished job's info, or None if none finished in time."""
+        x = dpsnn_job_info()
+        rc = lib().dpsnn_server_wait_any(self.h, -1.0 if timeout is None else timeout,
+                                         C.byref(x))
+        if rc == E_TIMEOUT:
+            return None
+        _check(rc)
+        return _info(x)
+
+    def job_network(self, job: int) -> Network:
+        """Read access to a DONE job's network (owned by the server)."""
+        info = self.query(job)
+        if info["status"] != JOB_DONE or not info["net"]:
+            raise DpsnnError(E_INVAL, f"job {job} is not done")
+        return Network._view(info["net"], self._cfgs[job])
+
+    def release(self, job: int):
+        _check(lib().dpsnn_server_release(self.h, job))
+        self._cfgs.pop(job, None)
+
+    def stats(self) -> dict:
+        s = dpsnn_server_stats()
+        _check(lib().dpsnn_server_get_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in dpsnn_server_stats._fields_}
+
+    def clock(self) -> float:
+        x = C.c_double()
+        _check(lib().dpsnn_server_clock(self.h, C.byref(x)))
+        return x.value

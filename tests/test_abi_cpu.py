@@ -68,3 +68,24 @@ def test_size_limits(dp):
     with pytest.raises(dp.DpsnnError):
         dp.footprint_bytes(W.make_config(grid_x=256, grid_y=256, neurons_per_column=1100,
                                          synapses_per_neuron=1))
+
+
+def test_server_argument_checks(dp):
+    # argument checks come before any device work
+    L = dp.lib()
+    h = C.c_void_p()
+    assert L.dpsnn_server_create(None, 0, 0, 0, C.byref(h)) == dp.E_INVAL
+    dev = dp.dpsnn_device()
+    dev.device = -1
+    assert L.dpsnn_server_create(C.byref(dev), 0, 0, 0, C.byref(h)) == dp.E_INVAL
+    assert not h.value
+    cfg = dp.to_config(W.tiny())
+    j = C.c_uint64()
+    assert L.dpsnn_server_submit(None, C.byref(cfg), 10, C.byref(j)) == dp.E_INVAL
+    info = dp.dpsnn_job_info()
+    assert L.dpsnn_server_wait_any(None, 0.0, C.byref(info)) == dp.E_INVAL
+    assert L.dpsnn_server_wait(None, 1, 0.0, C.byref(info)) == dp.E_INVAL
+    assert L.dpsnn_server_release(None, 1) == dp.E_INVAL
+    assert L.dpsnn_server_query(None, 1, C.byref(info)) == dp.E_INVAL
+    L.dpsnn_server_destroy(None)
+    assert C.sizeof(dp.dpsnn_job_info) == 8 + 4 + 4 + 4 + 4 + 8 + 4 * 8 + 8 + 160
