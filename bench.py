@@ -335,13 +335,104 @@ def bench_serving(args, mode):
     print(json.dumps(out))
 
 
+def bench_paper(args, mode):
+    """The paper's own experiment shapes on one GPU: the Table 1 scaling grids
+    (1000-neuron columns, M = 200, 76/12/8/4 % projection) and the Table 3
+    synapses-per-neuron sweep, each timed over args.paper_steps steps after
+    args.paper_warmup steps of evolution (the paper: 2 s after 8 s)."""
+    import torch
+    from paper_1310_8478_amd import dpsnn as dp
+    from paper_1310_8478_amd import workloads as W
+
+    torch.cuda.set_device(0)
+
+    def run(cfg, label):
+        S = cfg["grid_x"] * cfg["grid_y"] * cfg["neurons_per_column"] * cfg["synapses_per_neuron"]
+        N = cfg["grid_x"] * cfg["grid_y"] * cfg["neurons_per_column"]
+        try:
+            dp.footprint_bytes(cfg)
+        except dp.DpsnnError as e:
+            return {"synapses": S, "skipped": str(e)}
+        t0 = time.perf_counter()
+        net = dp.Network(cfg, device=0)
+        net.sync()
+        build_s = time.perf_counter() - t0
+        done = 0
+        while done < args.paper_warmup:
+            k = min(1000, args.paper_warmup - done)
+            net.step(k)
+            net.sync()
+            done += k
+        net.set_timing(True)
+        s0 = net.stats()
+        t0 = time.perf_counter()
+        done = 0
+        while done < args.paper_steps:
+            k = min(500, args.paper_steps - done)
+            net.step(k)
+            done += k
+        net.sync()
+        wall = time.perf_counter() - t0
+        s1 = net.stats()
+        net.close()
+        d = {k: s1[k] - s0[k] for k in s1}
+        sim_s = args.paper_steps / 1000.0
+        rate = d["spikes"] / N / sim_s
+        wps = wall / sim_s
+        print(f"[bench] paper {label}: {wps:.4f} wall s per sim s at {rate:.1f} Hz",
+              file=sys.stderr, flush=True)
+        return {"synapses": S, "neurons": N, "rate_hz": rate, "wall_s_per_sim_s": wps,
+                "normalized_s": wps / (rate * S) if rate > 0 else None,
+                "events_per_s": d["events"] / wall, "build_s": build_s,
+                "kernel_ms_per_step": {k: d[f"ms_{k}"] / args.paper_steps for k in KERNELS}}
+
+    t1 = []
+    for k, (gx, gy, rate, wps, norm) in enumerate(W.PAPER_TABLE1):
+        r = run(dict(W.paper_table1(k), sum_mode=mode), f"table1 {gx}x{gy}")
+        r.update(grid=f"{gx}x{gy}", paper_rate_hz=rate, paper_wall_s_per_sim_s=wps,
+                 paper_normalized_s=norm)
+        t1.append(r)
+    t3 = []
+    for k, (M, ncol, gx, gy, rate, rel) in enumerate(W.PAPER_TABLE3):
+        r = run(dict(W.paper_table3(k), sum_mode=mode), f"table3 M={M} {ncol}/col {gx}x{gy}")
+        r.update(M=M, neurons_per_column=ncol, grid=f"{gx}x{gy}", paper_rate_hz=rate,
+                 paper_relative_time=rel)
+        t3.append(r)
+    base = t3[0].get("normalized_s")
+    for r in t3:
+        r["relative_time"] = r["normalized_s"] / base if base and r.get("normalized_s") else None
+    head = max((r for r in t1 if "events_per_s" in r), key=lambda r: r["synapses"])
+    out = {
+        "metric": "synaptic events/s",
+        "value": head["events_per_s"],
+        "unit": "events/s",
+        "n_gpus": 1, "steps": args.paper_steps, "warmup": args.paper_warmup,
+        "ms_per_step": head["wall_s_per_sim_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if mode != W.SUM_FIXED else "f32+i64acc",
+        "data": "synthetic (seeded Philox networks and thalamic input, as in the paper)",
+        "config": {
+            "workload": (f"paper Table 1 grid {head['grid']} of 1000-neuron columns, M = 200, "
+                         f"76/12/8/4 % projection; value is this grid's events/s; the sweep "
+                         f"over Table 1 and Table 3 shapes follows"),
+            "sum_mode": args.mode,
+            "timed_steps": f"{args.paper_warmup}..{args.paper_warmup + args.paper_steps - 1}",
+        },
+        "paper_table1": t1,
+        "paper_table3": t3,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="large",
-                    choices=["tiny", "mid", "large", "batched", "serving"])
+                    choices=["tiny", "mid", "large", "batched", "serving", "paper"])
     ap.add_argument("--nets", type=int, default=32, help="networks in the batched workload")
     ap.add_argument("--requests", type=int, default=400, help="jobs in the serving workload")
     ap.add_argument("--rate", type=float, default=20.0, help="serving arrivals per second")
@@ -349,6 +440,8 @@ def main():
     ap.add_argument("--quantum", type=int, default=8, help="serving steps per quantum")
     ap.add_argument("--warmup-jobs", type=int, default=4)
     ap.add_argument("--jobs-out", default="", help="serving: write per-job records (JSON) here")
+    ap.add_argument("--paper-warmup", type=int, default=8000, help="paper: steps before timing")
+    ap.add_argument("--paper-steps", type=int, default=2000, help="paper: timed steps")
     ap.add_argument("--mode", default="fixed", choices=["fixed", "atomic", "ordered"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -382,6 +475,8 @@ def main():
         return bench_batched(args, mode)
     if args.workload == "serving":
         return bench_serving(args, mode)
+    if args.workload == "paper":
+        return bench_paper(args, mode)
     make, _ = W.WORKLOADS[args.workload]
     cfg = make(sum_mode=mode)
     torch.cuda.set_device(0)

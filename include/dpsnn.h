@@ -74,7 +74,7 @@ typedef struct dpsnn_config {
     float    a_plus, a_minus, tau_plus, tau_minus;  /* STDP rule (Sec. 2) */
     uint32_t weight_update_period;    /* steps; 0 disables consolidation */
     float    wu_bias, sd_decay;       /* w += bias + (P - D); P <- decay*(P - D) */
-    float    thalamic_rate;           /* events per column per ms, [0, 64) */
+    float    thalamic_rate;           /* events per column per ms, [0, 1024) */
     float    thalamic_current;        /* mV per thalamic event */
     uint64_t seed;                    /* Philox key for connectivity and input */
     uint32_t sum_mode;                /* DPSNN_SUM_* */

@@ -99,6 +99,7 @@ static uint32_t mulhi_range(uint32_t x, uint32_t n)
 
 #define TAG_SYN  0x53594E00u   /* counter word 2 for synapse draws */
 #define TAG_THAL 0x5448414Cu   /* counter word 2 for thalamic draws */
+#define ORC_MAX_THAL 1024u     /* thalamic events per column per ms (rate < 1024) */
 
 static void draw(const orc_config *cfg, uint32_t w0, uint32_t w1, uint32_t tag, uint32_t w3,
                  uint32_t out[4])
@@ -543,10 +544,10 @@ static int step_once(orc_net *net)
     }
 
     /* External input: thalamic picks of every column, then the stimulus list. */
-    uint32_t picks[64];
+    uint32_t picks[ORC_MAX_THAL];
     for (uint32_t c = 0; c < net->C; ++c) {
-        uint32_t n = orc_thalamic(cfg, c, t, picks, 64);
-        if (n > 64) return -3;
+        uint32_t n = orc_thalamic(cfg, c, t, picks, ORC_MAX_THAL);
+        if (n > ORC_MAX_THAL) return -3;
         for (uint32_t k = 0; k < n; ++k) {
             uint32_t id = c * Ncol + picks[k];
             if (fixed) net->acci[id] += q32(cfg->thalamic_current);

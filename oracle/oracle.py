@@ -122,9 +122,9 @@ def synapse(cfg: dict, i: int, j: int):
 
 def thalamic(cfg: dict, c: int, t: int):
     cc = to_cfg(cfg)
-    buf = (C.c_uint32 * 64)()
-    n = lib().orc_thalamic(C.byref(cc), c, t, buf, 64)
-    return [buf[k] for k in range(min(n, 64))]
+    buf = (C.c_uint32 * 1024)()
+    n = lib().orc_thalamic(C.byref(cc), c, t, buf, 1024)
+    return [buf[k] for k in range(min(n, 1024))]
 
 
 def tp(cfg: dict, delta: int) -> float:

@@ -75,8 +75,8 @@ int validate(const dpsnn_config* c, Derived* o) {
         return fail(DPSNN_E_INVAL, "STDP time constants must be in [1e-3, 1000] ms");
     if (!finite_in(c->wu_bias, -1000.f, 1000.f) || !finite_in(c->sd_decay, -1000.f, 1000.f))
         return fail(DPSNN_E_INVAL, "consolidation constants must be finite");
-    if (!(std::isfinite(c->thalamic_rate) && c->thalamic_rate >= 0.f && c->thalamic_rate < 64.f))
-        return fail(DPSNN_E_INVAL, "thalamic_rate must be in [0, 64)");
+    if (!(std::isfinite(c->thalamic_rate) && c->thalamic_rate >= 0.f && c->thalamic_rate < 1024.f))
+        return fail(DPSNN_E_INVAL, "thalamic_rate must be in [0, 1024)");
     if (!finite_in(c->thalamic_current, -1000.f, 1000.f))
         return fail(DPSNN_E_INVAL, "thalamic_current must be finite, |x| <= 1000");
     if (c->sum_mode > 2u) return fail(DPSNN_E_INVAL, "sum_mode must be 0, 1 or 2");

@@ -49,7 +49,7 @@ def test_default_config_and_footprint(dp):
 @pytest.mark.parametrize("field,value", [
     ("grid_x", 0), ("neurons_per_column", 1), ("synapses_per_neuron", 0),
     ("max_delay", 0), ("max_delay", 32), ("exc_fraction", 0.0), ("conn_mode", 2),
-    ("thalamic_rate", 64.0), ("thalamic_rate", -1.0), ("tau_plus", 0.0),
+    ("thalamic_rate", 1024.0), ("thalamic_rate", -1.0), ("tau_plus", 0.0),
     ("w_max", float("nan")), ("sum_mode", 3), ("raster_steps", 5),
 ])
 def test_invalid_configs_rejected(dp, field, value):

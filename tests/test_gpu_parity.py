@@ -162,6 +162,42 @@ def test_large_column_dense_regime_bitexact(dp, orc, mode):
     assert_bitexact(g, o)
 
 
+WIDE = {
+    "10240x2": dict(grid=(2, 1), neurons_per_column=10240),
+    "12800x1": dict(grid=(1, 1), neurons_per_column=12800),
+}
+
+
+@pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
+@pytest.mark.parametrize("shape", list(WIDE))
+def test_wide_column_bitexact(dp, orc, shape, mode):
+    # the wide columns of the paper's synapses-per-neuron sweep (Table 3):
+    # the LDS current and spike-history windows do not fit, so delivery and
+    # LTP take their global-memory paths; 32-bit target indices
+    cfg = W.paper_shaped(M=60, weight_update_period=60, thalamic_rate=60.0, w_exc_init=9.0,
+                         sum_mode=mode, **WIDE[shape])
+    T = 150
+    _say(f"wide column {shape} mode {mode}")
+    g = gpu_run(dp, cfg, T)
+    o = oracle_run(orc, cfg, T)
+    assert len(o["tt"]) > 50000
+    assert_bitexact(g, o)
+    assert g["stats"]["events"] == o["counters"]["events"]
+
+
+@pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
+def test_high_thalamic_rate_bitexact(dp, orc, mode):
+    # hundreds of thalamic events per column per ms (the drive of wide columns)
+    cfg = W.make_config(grid_x=2, grid_y=2, neurons_per_column=300, synapses_per_neuron=40,
+                        thalamic_rate=200.5, weight_update_period=50, sum_mode=mode)
+    T = 120
+    _say(f"high thalamic rate mode {mode}")
+    g = gpu_run(dp, cfg, T)
+    o = oracle_run(orc, cfg, T)
+    assert o["counters"]["thalamic"] > 4 * 200 * T
+    assert_bitexact(g, o)
+
+
 TUNINGS = [
     ((0, 256),), ((0, 512), (3, 1)), ((2, 0),), ((3, 2), (1, 1024)), ((2, 0), (0, 256), (3, 1)),
 ]

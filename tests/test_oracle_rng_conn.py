@@ -191,12 +191,17 @@ def test_thalamic_counts_and_uniformity(orc):
     assert stats.chisquare(np.bincount(flat, minlength=50)).pvalue > 1e-4
 
 
-@pytest.mark.parametrize("rate", [0.0, 0.5, 1.5, 2.0, 4.25])
+@pytest.mark.parametrize("rate", [0.0, 0.5, 1.5, 2.0, 4.25, 200.5, 1023.75])
 def test_thalamic_fractional_rate(orc, rate):
     cfg = W.make_config(grid_x=2, grid_y=2, neurons_per_column=40,
                         thalamic_rate=float(np.float32(rate)))
-    n = np.array([len(orc.thalamic(cfg, c, t)) for c in range(4) for t in range(4000)])
+    steps = 4000 if rate < 10 else 300
+    picks = [orc.thalamic(cfg, c, t) for c in range(4) for t in range(steps)]
+    n = np.array([len(p) for p in picks])
     whole = int(np.floor(rate))
+    if rate >= 10:   # many picks per step: each a uniform neuron of the column
+        flat = np.concatenate([np.asarray(p) for p in picks])
+        assert stats.chisquare(np.bincount(flat, minlength=40)).pvalue > 1e-4
     assert set(np.unique(n)) <= {whole, whole + 1}
     frac = rate - whole
     # mean within 5 sigma of the Bernoulli(frac) expectation
