@@ -363,6 +363,9 @@ def bench_paper(args, mode):
             net.step(k)
             net.sync()
             done += k
+            if done % 2000 == 0:
+                print(f"[bench] paper {label}: warm-up {done}/{args.paper_warmup}",
+                      file=sys.stderr, flush=True)
         net.set_timing(True)
         s0 = net.stats()
         t0 = time.perf_counter()

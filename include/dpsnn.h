@@ -172,7 +172,9 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
 /* Launch-shape knobs (results never depend on them): key 0 = delivery block
  * size, 1 = LTP block size, 2 = LDS current window (1 on, 0 off),
  * 3 = events-per-lane unroll in delivery (1, 2, 4 or 8), 4 = LDS copy of the
- * targets' spike ages in delivery (1 on, 0 off). */
+ * targets' spike ages in delivery (1 on, 0 off), 5 = workgroups per column in
+ * delivery and LTP (0 = automatic: networks with few columns split each
+ * column's work; 1 .. 1024 = that many; summation mode ORDERED always 1). */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 
 /* Online autotuner of the launch shapes (the knobs of dpsnn_set_tuning):

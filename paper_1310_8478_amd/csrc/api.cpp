@@ -255,6 +255,7 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
     L.K = cnt;
     L.max_ncol = 0;
     L.max_w = 0;
+    L.min_col_syn = ~0ull;
     L.sum_mode = m[0]->cfg.sum_mode;
     L.tgt16 = m[0]->tgt16;
     std::vector<uint2>& col = L.host_col;
@@ -270,6 +271,7 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
         const Dims& d = m[k]->d;
         L.max_ncol = std::max(L.max_ncol, d.Ncol);
         L.max_w = std::max(L.max_w, d.W);
+        L.min_col_syn = std::min<uint64_t>(L.min_col_syn, (uint64_t)d.Ncol * d.M);
         for (uint32_t c = 0; c < d.C; ++c) col.push_back(make_uint2(k, c));
         for (uint32_t w0 = 0; w0 < d.C * d.W; w0 += 4) neu.push_back(make_uint2(k, w0));
         const uint64_t nch = (m[k]->S_exc + wchunk - 1) / wchunk;
@@ -330,6 +332,10 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
             return DPSNN_OK;
         case 4:
             tn.age = value ? 1u : 0u;
+            return DPSNN_OK;
+        case 5:
+            if (value > 1024) return fail(DPSNN_E_INVAL, "column parts must be 0 (automatic) to 1024");
+            tn.parts = value;
             return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");

@@ -277,6 +277,30 @@ __device__ __forceinline__ WaveRange wave_range(uint32_t E) {
     return w;
 }
 
+// Part p of P of the items [0, E): equal shares, in order.
+__device__ __forceinline__ void part_slice(uint32_t E, uint32_t p, uint32_t P, uint32_t& lo,
+                                           uint32_t& hi) {
+    lo = (uint32_t)(((uint64_t)E * p) / P);
+    hi = (uint32_t)(((uint64_t)E * (p + 1u)) / P);
+}
+
+// Boundary p of P of the positions [lo, hi), inner boundaries rounded up to a
+// multiple of 4 (non-decreasing in p; boundary 0 is lo and boundary P is hi).
+__device__ __forceinline__ uint32_t part_bound4(uint32_t lo, uint32_t hi, uint32_t p, uint32_t P) {
+    if (p == 0) return lo;
+    if (p >= P) return hi;
+    const uint32_t x = lo + (uint32_t)(((uint64_t)(hi - lo) * p) / P);
+    return min(hi, (x + 3u) & ~3u);
+}
+
+// wave_range over the items [lo, hi).
+__device__ __forceinline__ WaveRange wave_range_in(uint32_t lo, uint32_t hi) {
+    WaveRange w = wave_range(hi - lo);
+    w.begin += lo;
+    w.end += lo;
+    return w;
+}
+
 // Run of event e for a lane, starting from the wavefront's cursor r (the run
 // of the slice base): the common case is one comparison.
 __device__ __forceinline__ uint32_t lane_run(const uint32_t* pref, uint32_t r, uint32_t nr,

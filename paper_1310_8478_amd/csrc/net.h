@@ -16,6 +16,7 @@ namespace dpsnn {
 // Launch-shape knobs; results never depend on them.
 struct Tuning {
     uint32_t deliver_block = 1024, ltp_block = 1024, window = 1, unroll = 8, age = 1;
+    uint32_t parts = 0;           // workgroups per column (0: chosen per launch set)
     size_t max_lds = 65536;
 };
 
@@ -46,6 +47,7 @@ struct LaunchSet {
     std::vector<uint2*> bmap_wu;
     std::vector<uint32_t> n_wu;
     uint32_t max_ncol = 0, max_w = 0, sum_mode = 0;
+    uint64_t min_col_syn = 0;     // fewest synapses of one column over the members
     bool tgt16 = true;
     // host copies of the uploaded tables
     std::vector<NetDesc> host_descs;

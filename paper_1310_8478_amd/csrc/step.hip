@@ -28,8 +28,11 @@ namespace {
 // ---------------------------------------------------------------------------
 template <int U>
 __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
-                                              const uint2* __restrict__ bmap, uint32_t allow_stage) {
-    const uint2 br = bmap[blockIdx.x];
+                                              const uint2* __restrict__ bmap, uint32_t allow_stage,
+                                              uint32_t nparts) {
+    // block: part `part` of the column of map entry blockIdx.x / nparts
+    const uint2 br = bmap[blockIdx.x / nparts];
+    const uint32_t part = blockIdx.x % nparts;
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
     const uint32_t t = *nd.t_ptr;
@@ -71,7 +74,7 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
     const uint32_t be_ = block_scan(ce, sh, nends);
     if (tid < kSlots) smap[tid] = srcmap[ct * kSlots + tid];
     if (tid < 64) tph[tid] = tid < tp_len ? tp[tid] : 0.0f;
-    const bool stage = allow_stage && (nsp * 8u >= d.Ncol);
+    const bool stage = allow_stage && nparts == 1u && (nsp * 8u >= d.Ncol);
     __syncthreads();
     if (stage) {
         const uint32_t nwin = kSlots * d.Ncol;
@@ -85,8 +88,10 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
     if (nsp == d.Ncol) {
         // every neuron of the column fired: its reverse rows form one block
         __syncthreads();
-        const uint32_t x_lo = rowptr[ct * d.Ncol];
-        const uint32_t x_hi = rowptr[(ct + 1) * d.Ncol];
+        const uint32_t c_lo = rowptr[ct * d.Ncol];
+        const uint32_t c_hi = rowptr[(ct + 1) * d.Ncol];
+        const uint32_t x_lo = part_bound4(c_lo, c_hi, part, nparts);
+        const uint32_t x_hi = part_bound4(c_lo, c_hi, part + 1u, nparts);
         const uint32_t total = x_hi - x_lo;
         // LTP of one reverse entry: returns the new P
         auto ltp_one = [&](uint32_t sd, float pv) -> float {
@@ -195,7 +200,9 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
             pref[tid] = ex;
         }
         __syncthreads();
-        const WaveRange wr_ = wave_range(E);
+        uint32_t plo, phi;
+        part_slice(E, part, nparts, plo, phi);
+        const WaveRange wr_ = wave_range_in(plo, phi);
         uint32_t cur = wr_.begin < wr_.end ? upper_run(pref, 0u, nr, wr_.begin) : 0u;
         for (uint32_t eb = wr_.begin; eb < wr_.end; eb += 64u * U) {
             uint32_t xs[U], sd[U];
@@ -237,10 +244,10 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
                 P[xs[q]] = pv[q] + a;
             }
         }
-        visits += E;
+        visits += phi - plo;
         __syncthreads();
     }
-    if (tid == 0) atomicAdd(&stats[ct & 63].ltp_visits, visits);
+    if (tid == 0 && visits) atomicAdd(&stats[ct & 63].ltp_visits, visits);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,8 +262,10 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
 template <bool FIXED, bool WINDOW, typename TgtT, int U>
 __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nds,
                                                   const uint2* __restrict__ bmap,
-                                                  uint32_t allow_age) {
-    const uint2 br = bmap[blockIdx.x];
+                                                  uint32_t allow_age, uint32_t nparts) {
+    // block: part `part` of the column of map entry blockIdx.x / nparts
+    const uint2 br = bmap[blockIdx.x / nparts];
+    const uint32_t part = blockIdx.x % nparts;
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
     const uint32_t t = *nd.t_ptr;
@@ -325,13 +334,14 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
     }
     full = __syncthreads_and(full);
     if (full) {
-        const uint32_t cb = c * d.Ncol * d.M;
-        const uint32_t total = d.Ncol * d.M;
+        const uint32_t c0 = c * d.Ncol * d.M;
+        const uint32_t cb = part_bound4(c0, c0 + d.Ncol * d.M, part, nparts);
+        const uint32_t total = part_bound4(c0, c0 + d.Ncol * d.M, part + 1u, nparts) - cb;
         const size_t s1 = (size_t)c * d.segs;
         // inhibitory synapses all have delay 1: one range of the d = 1 block
         const uint32_t inh_lo = d.Ne < d.Ncol ? seg_off[s1 + d.Ne] : cb;
         const uint32_t inh_hi = d.Ne < d.Ncol ? seg_off[s1 + d.Ncol] : cb;
-        if (allow_age) {
+        if (allow_age && total >= nwin) {  // block-uniform
             for (uint32_t x = tid; x < nwin; x += BS) {
                 const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
                 const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
@@ -516,7 +526,9 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
                 excf[tid] = isx;
                 pref[tid] = ex;
             }
-            if (allow_age && !staged && E >= nwin) {  // block-uniform
+            uint32_t plo, phi;
+            part_slice(E, part, nparts, plo, phi);
+            if (allow_age && !staged && phi - plo >= nwin) {  // block-uniform
                 for (uint32_t x = tid; x < nwin; x += BS) {
                     const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
                     const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
@@ -526,7 +538,7 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
                 staged = true;
             }
             __syncthreads();
-            const WaveRange wr_ = wave_range(E);
+            const WaveRange wr_ = wave_range_in(plo, phi);
             uint32_t cur = wr_.begin < wr_.end ? upper_run(pref, 0u, nr, wr_.begin) : 0u;
             for (uint32_t eb = wr_.begin; eb < wr_.end; eb += 64u * U) {
                 uint32_t pos[U], wi[U];
@@ -583,7 +595,7 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
                     }
                 }
             }
-            events += E;
+            events += phi - plo;
             __syncthreads();
         }
     }
@@ -740,29 +752,43 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
     const uint32_t l = wd * 64u + lane;
     const bool valid = wave_ok && l < d.Ncol;
     bool fired = false;
+    // Thalamic picks of column c in step t: pick p is word 1 + p % 3 of
+    // generator call p / 3, and word 0 of call 0 decides the fractional
+    // count.  The 64 lanes of a wavefront draw the calls in parallel and
+    // count the hits on their own 64 neurons in LDS.
+    __shared__ uint32_t thc[4][64];
+    const uint32_t wv = threadIdx.x >> 6;
+    thc[wv][lane] = 0u;
+    __syncthreads();
+    if (wave_ok && (thal_whole | thal_thr)) {  // wavefront-uniform
+        uint32_t n = 0;
+        for (uint32_t call0 = 0;; call0 += 64u) {
+            const uint32_t call = call0 + lane;
+            uint32_t z[4] = {c, t, kTagThal, call};
+            philox10(z, d.key0, d.key1);
+            if (call0 == 0) n = thal_whole + (__shfl(z[0], 0, 64) < thal_thr ? 1u : 0u);
+#pragma unroll
+            for (uint32_t q = 0; q < 3; ++q) {
+                if (3u * call + q < n) {
+                    const uint32_t rel = pick(z[1 + q], d.Ncol) - wd * 64u;
+                    if (rel < 64u) atomicAdd(&thc[wv][rel], 1u);
+                }
+            }
+            if (n <= 3u * (call0 + 64u)) break;
+        }
+    }
+    __syncthreads();
     if (valid) {
         const uint32_t k = c * d.Ncol + l;
-        // external input: thalamic picks of column c in step t, then stimulus
-        uint32_t y[4] = {c, t, kTagThal, 0u};
-        philox10(y, d.key0, d.key1);
-        const uint32_t n = thal_whole + (y[0] < thal_thr ? 1u : 0u);
-        uint32_t z[4] = {y[0], y[1], y[2], y[3]};
+        // external input: this neuron's thalamic hits, then the stimulus
+        const uint32_t hits = thc[wv][lane];
         long long a64 = 0;
         float a32 = 0.0f;
         if (MODE == DPSNN_SUM_FIXED) a64 = ((long long*)acc_v)[k];
         if (MODE == DPSNN_SUM_ATOMIC) a32 = ((float*)acc_v)[k];
         const long long q_thal = to_fixed(thal_mv);
-        for (uint32_t p = 0; p < n; ++p) {
-            const uint32_t call = p / 3u, word = 1u + p % 3u;
-            if (word == 1u && call > 0u) {
-                z[0] = c; z[1] = t; z[2] = kTagThal; z[3] = call;
-                philox10(z, d.key0, d.key1);
-            }
-            if (pick(z[word], d.Ncol) == l) {
-                if (MODE == DPSNN_SUM_FIXED) a64 += q_thal;
-                else a32 = a32 + thal_mv;
-            }
-        }
+        if (MODE == DPSNN_SUM_FIXED) a64 += (long long)hits * q_thal;
+        else for (uint32_t h = 0; h < hits; ++h) a32 = a32 + thal_mv;
         for (uint32_t e = sb; e < se; ++e) {
             if (stim_id[e] == k) {
                 if (MODE == DPSNN_SUM_FIXED) a64 += to_fixed(stim_mv[e]);
@@ -822,7 +848,6 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
         else ((float*)acc_v)[k] = 0.0f;
     }
     const unsigned long long mask = __ballot(fired);
-    const uint32_t wv = threadIdx.x >> 6;
     if (lane == 0) {
         if (wave_ok) ring[((size_t)((t + 1u) % d.R) * d.C + c) * d.W + wd] = mask;
         wsum[wv] = (uint32_t)__popcll(mask);
@@ -874,8 +899,23 @@ void allow_lds(K kernel, size_t bytes) {
                                   (int)bytes);
 }
 
+// Workgroups per column for delivery and LTP: sets with fewer columns than
+// a few per compute unit split every column into equal parts, each part at
+// least about 8 K synapses of the smallest column.  The results do not
+// depend on the split.
+uint32_t column_parts(const LaunchSet& L, const Tuning& tune) {
+    if (L.sum_mode == DPSNN_SUM_ORDERED || L.n_col == 0) return 1u;
+    if (tune.parts) return tune.parts;
+    const uint32_t target = 512u;  // two workgroups per compute unit
+    if (L.n_col >= target) return 1u;
+    const uint64_t want = (target + L.n_col - 1u) / L.n_col;
+    const uint64_t cap = std::max<uint64_t>(1u, L.min_col_syn / 8192u);
+    return (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, cap), 1024u);
+}
+
 template <typename TgtT>
-hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, Net* const* members) {
+hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, Net* const* members,
+                          uint32_t nparts) {
     if (L.sum_mode == DPSNN_SUM_ORDERED) {
         // one network only (checked when the set is made)
         Net& n = *members[0];
@@ -902,8 +942,8 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
 #define DPSNN_DELIVER(FX, WN, UU)                                                              \
     do {                                                                                       \
         allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                           \
-        hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(L.n_col), dim3(BS), lds, stream, \
-                           L.descs, L.bmap_col, allow_age);                                    \
+        hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(L.n_col * nparts), dim3(BS), lds, \
+                           stream, L.descs, L.bmap_col, allow_age, nparts);                    \
     } while (0)
     if (tune.unroll == 1) {
         if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 1); else DPSNN_DELIVER(true, false, 1); }
@@ -982,13 +1022,15 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune, Timers& tm, hipStre
         const uint32_t allow = (base + hw <= tune.max_lds) ? 1u : 0u;
         const size_t lds = base + (allow ? hw : 0);
         allow_lds(k_ltp<4>, lds);
+        const uint32_t nparts = column_parts(L, tune);
         tm.begin(0, stream);
-        hipLaunchKernelGGL(k_ltp<4>, dim3(L.n_col), dim3(BS), lds, stream, L.descs, L.bmap_col, allow);
+        hipLaunchKernelGGL(k_ltp<4>, dim3(L.n_col * nparts), dim3(BS), lds, stream, L.descs,
+                           L.bmap_col, allow, nparts);
         tm.end(stream);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         tm.begin(1, stream);
-        e = L.tgt16 ? launch_deliver<uint16_t>(L, tune, stream, members)
-                    : launch_deliver<uint32_t>(L, tune, stream, members);
+        e = L.tgt16 ? launch_deliver<uint16_t>(L, tune, stream, members, nparts)
+                    : launch_deliver<uint32_t>(L, tune, stream, members, nparts);
         tm.end(stream);
         if (e != hipSuccess) return e;
     }

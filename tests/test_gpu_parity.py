@@ -200,7 +200,23 @@ def test_high_thalamic_rate_bitexact(dp, orc, mode):
 
 TUNINGS = [
     ((0, 256),), ((0, 512), (3, 1)), ((2, 0),), ((3, 2), (1, 1024)), ((2, 0), (0, 256), (3, 1)),
+    ((5, 1),), ((5, 3),), ((5, 7), (2, 0)), ((5, 64), (0, 256), (1, 512)),
 ]
+
+
+def test_dense_regime_column_parts(dp):
+    # the all-firing regime through the dense paths, one column split into
+    # many parts against the unsplit column
+    cfg = W.make_config(grid_x=1, grid_y=2, synapses_per_neuron=625, weight_update_period=110)
+    T = 140
+    _say("dense regime, column parts 1 vs 13 vs 200")
+    ref = gpu_run(dp, cfg, T, tuning=((5, 1),), conn=False)
+    assert (np.bincount(ref["tt"], minlength=T + 1)[110:] == 2500).sum() >= 20
+    for p in (13, 200):
+        g = gpu_run(dp, cfg, T, tuning=((5, p),), conn=False)
+        assert_bitexact(g, ref, conn=False)
+        assert g["stats"]["events"] == ref["stats"]["events"]
+        assert g["stats"]["ltp_visits"] == ref["stats"]["ltp_visits"]
 
 
 @pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
