@@ -125,7 +125,9 @@ int dpsnn_footprint_bytes(const dpsnn_config *cfg, uint64_t *bytes);
 int dpsnn_build_network(const dpsnn_config *cfg, const dpsnn_device *dev, dpsnn_net **out);
 
 /* Enqueue n_steps 1 ms steps (Sec. 2, loop items 2.1-2.7, plus the periodic
- * consolidation).  Asynchronous on the network's stream. */
+ * consolidation).  Asynchronous on the network's stream, except that the
+ * call waits when it gets more than about 16 steps ahead of the device (the
+ * automatic launch shapes follow a measured event rate at most that stale). */
 int dpsnn_step(dpsnn_net *net, uint32_t n_steps);
 
 /* Wait for all enqueued work of the network. */
@@ -170,11 +172,13 @@ int dpsnn_set_stimulus(dpsnn_net *net, const uint32_t *t, const uint32_t *id,
 int dpsnn_set_timing(dpsnn_net *net, int enable);
 
 /* Launch-shape knobs (results never depend on them): key 0 = delivery block
- * size, 1 = LTP block size, 2 = LDS current window (1 on, 0 off),
+ * size, 1 = LTP block size, 2 = LDS current window in delivery (1 = over all
+ * 13 reachable columns, 2 = over the own column only, 0 = off),
  * 3 = events-per-lane unroll in delivery (1, 2, 4 or 8), 4 = LDS copy of the
  * targets' spike ages in delivery (1 on, 0 off), 5 = workgroups per column in
  * delivery and LTP (0 = automatic: networks with few columns split each
- * column's work; 1 .. 1024 = that many; summation mode ORDERED always 1). */
+ * column's work; 1 .. 1024 = that many; summation mode ORDERED always 1),
+ * 6 = LDS copy of the sources' spike history in LTP (1 allowed, 0 off). */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 
 /* Online autotuner of the launch shapes (the knobs of dpsnn_set_tuning):

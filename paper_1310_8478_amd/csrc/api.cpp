@@ -153,6 +153,7 @@ void release(Net* n) {
     if (!n) return;
     (void)hipSetDevice(n->dev.device);
     (void)hipStreamSynchronize(n->stream);
+    release_launch_set_host(n->solo);
     for (auto& a : n->allocs) dfree(*n, a.p, a.bytes);
     n->allocs.clear();
     n->timers.release();
@@ -239,6 +240,19 @@ void* dev_alloc(const dpsnn_device& dev, hipStream_t stream, size_t bytes,
     return p;
 }
 
+void release_launch_set_host(LaunchSet& L) {
+    if (L.ev_copied) {
+        if (L.copy_pending) (void)hipEventSynchronize(L.ev_copied);
+        (void)hipEventDestroy(L.ev_copied);
+        L.ev_copied = nullptr;
+    }
+    if (L.ev_host) {
+        (void)hipHostFree(L.ev_host);
+        L.ev_host = nullptr;
+    }
+    L.copy_pending = false;
+}
+
 void free_tracked(const dpsnn_device& dev, hipStream_t stream, std::vector<Net::Alloc>& allocs) {
     for (auto& a : allocs) {
         if (dev.free) dev.free(a.p, a.bytes, stream, dev.ctx);
@@ -280,6 +294,27 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
     }
     L.n_col = (uint32_t)col.size();
     L.n_neu = (uint32_t)neu.size();
+    {
+        double neurons = 0.0, est = 0.0;
+        for (uint32_t k = 0; k < cnt; ++k) {
+            neurons += (double)m[k]->d.N;
+            est += m[k]->per_col * (double)m[k]->d.C;
+        }
+        L.avg_nwin = L.n_col ? (double)kSlots * neurons / (double)L.n_col : 0.0;
+        L.per_col = L.n_col ? est / (double)L.n_col : 0.0;  // carried over from earlier sets
+        L.steps = L.copy_steps = L.base_steps = L.base_count = 0;
+        L.copy_pending = false;
+    }
+    L.ev_count = (unsigned long long*)dev_alloc(dev, stream, sizeof(unsigned long long), track);
+    if (!L.ev_count) return fail(DPSNN_E_NOMEM, "launch tables");
+    DPSNN_HIP(hipMemsetAsync(L.ev_count, 0, sizeof(unsigned long long), stream));
+    if (!L.ev_host) {
+        void* hp = nullptr;
+        if (hipHostMalloc(&hp, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+            return fail(DPSNN_E_NOMEM, "pinned regime counter");
+        L.ev_host = (unsigned long long*)hp;
+    }
+    if (!L.ev_copied) DPSNN_HIP(hipEventCreateWithFlags(&L.ev_copied, hipEventDisableTiming));
     L.descs = (NetDesc*)dev_alloc(dev, stream, sizeof(NetDesc) * cnt, track);
     L.bmap_col = (uint2*)dev_alloc(dev, stream, sizeof(uint2) * col.size(), track);
     L.bmap_neu = (uint2*)dev_alloc(dev, stream, sizeof(uint2) * neu.size(), track);
@@ -315,15 +350,18 @@ int refresh_descs(LaunchSet& L, Net* const* m, hipStream_t stream) {
 int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
     switch (key) {
         case 0:
-            if (value != 256 && value != 512 && value != 1024) return fail(DPSNN_E_INVAL, "delivery block must be 256, 512 or 1024");
+            if (value && value != 256 && value != 512 && value != 1024)
+                return fail(DPSNN_E_INVAL, "delivery block must be 0 (automatic), 256, 512 or 1024");
             tn.deliver_block = value;
             return DPSNN_OK;
         case 1:
-            if (value != 256 && value != 512 && value != 1024) return fail(DPSNN_E_INVAL, "LTP block must be 256, 512 or 1024");
+            if (value && value != 256 && value != 512 && value != 1024)
+                return fail(DPSNN_E_INVAL, "LTP block must be 0 (automatic), 256, 512 or 1024");
             tn.ltp_block = value;
             return DPSNN_OK;
         case 2:
-            tn.window = value ? 1u : 0u;
+            if (value > 3) return fail(DPSNN_E_INVAL, "window must be 0 (off), 1 (all columns), 2 (own column) or 3 (automatic)");
+            tn.window = value;
             return DPSNN_OK;
         case 3:
             if (value != 1 && value != 2 && value != 4 && value != 8)
@@ -331,11 +369,16 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
             tn.unroll = value;
             return DPSNN_OK;
         case 4:
-            tn.age = value ? 1u : 0u;
+            if (value > 2) return fail(DPSNN_E_INVAL, "age window must be 0 (off), 1 (on) or 2 (automatic)");
+            tn.age = value;
             return DPSNN_OK;
         case 5:
             if (value > 1024) return fail(DPSNN_E_INVAL, "column parts must be 0 (automatic) to 1024");
             tn.parts = value;
+            return DPSNN_OK;
+        case 6:
+            if (value > 2) return fail(DPSNN_E_INVAL, "LTP staging must be 0 (off), 1 (on) or 2 (automatic)");
+            tn.ltp_stage = value;
             return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");
@@ -912,6 +955,7 @@ int dpsnn_batch_create(dpsnn_net* const* nets, uint32_t n_nets, dpsnn_batch** ou
     b->tune = m[0]->tune;
     int rc = make_launch_set(b->L, b->members.data(), n_nets, b->dev, b->stream, &b->allocs, true);
     if (rc) {
+        release_launch_set_host(b->L);
         free_tracked(b->dev, b->stream, b->allocs);
         delete b;
         return rc;
@@ -976,6 +1020,7 @@ void dpsnn_batch_destroy(dpsnn_batch* b) {
     if (!b) return;
     (void)hipSetDevice(b->dev.device);
     (void)hipStreamSynchronize(b->stream);
+    release_launch_set_host(b->L);
     free_tracked(b->dev, b->stream, b->allocs);
     b->timers.release();
     for (Net* x : b->members) x->in_batch = false;

@@ -13,10 +13,18 @@
 
 namespace dpsnn {
 
-// Launch-shape knobs; results never depend on them.
+// Launch-shape knobs; results never depend on them.  "Auto" values follow the
+// launch set's measured regime: sparse (at least 2048 columns, and a source
+// column delivers fewer events per step than its current window has entries)
+// or dense.
 struct Tuning {
-    uint32_t deliver_block = 1024, ltp_block = 1024, window = 1, unroll = 8, age = 1;
+    uint32_t deliver_block = 0;   // 256, 512, 1024; 0 auto (sparse 256, dense 1024)
+    uint32_t ltp_block = 0;       // 256, 512, 1024; 0 auto (sparse 256, dense 1024)
+    uint32_t window = 3;          // 0 off, 1 all 13 columns, 2 own column; 3 auto (2 / 1)
+    uint32_t unroll = 8;
+    uint32_t age = 2;             // LDS target spike ages: 0 off, 1 on, 2 auto (off / on)
     uint32_t parts = 0;           // workgroups per column (0: chosen per launch set)
+    uint32_t ltp_stage = 2;       // LDS source spike history in LTP: 0, 1, 2 auto (0 / 1)
     size_t max_lds = 65536;
 };
 
@@ -48,7 +56,16 @@ struct LaunchSet {
     std::vector<uint32_t> n_wu;
     uint32_t max_ncol = 0, max_w = 0, sum_mode = 0;
     uint64_t min_col_syn = 0;     // fewest synapses of one column over the members
+    double avg_nwin = 0.0;        // mean current-window entries (13 x Ncol) per column
     bool tgt16 = true;
+    // regime estimate: delivered events per column and step, from a device
+    // counter copied to pinned host memory every few steps without waiting
+    unsigned long long* ev_count = nullptr;  // device (one of the set's tables)
+    unsigned long long* ev_host = nullptr;   // pinned host copy
+    hipEvent_t ev_copied = nullptr;
+    bool copy_pending = false;
+    uint64_t steps = 0, copy_steps = 0, base_steps = 0, base_count = 0;
+    double per_col = 0.0;
     // host copies of the uploaded tables
     std::vector<NetDesc> host_descs;
     std::vector<uint2> host_col, host_neu;
@@ -126,6 +143,7 @@ struct Net {
     Timers timers;
     LaunchSet solo;               // this network alone
     bool desc_dirty = true;
+    double per_col = 0.0;         // last regime estimate of a set holding this network
 
     NetDesc make_desc() const;
 };
@@ -140,6 +158,9 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
                     hipStream_t stream, std::vector<Net::Alloc>* track, bool sync);
 // Frees every device allocation of n (after synchronising its stream) and n.
 void destroy_net(Net* n);
+// Host resources of a launch set (pinned copy, event); the device tables are
+// freed with their owner's tracked allocations.
+void release_launch_set_host(LaunchSet& L);
 
 // launchers (return hipError_t)
 hipError_t launch_build(Net& n);

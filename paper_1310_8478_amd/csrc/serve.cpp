@@ -223,7 +223,10 @@ void dpsnn_server::complete(Quantum& q, std::vector<hipEvent_t>& pool) {
         cv_admit.notify_one();
     }
     dpsnn_device sdev = dev;
-    for (auto& g : q.retired) free_tracked(sdev, s_step, g->allocs);
+    for (auto& g : q.retired) {
+        release_launch_set_host(g->L);
+        free_tracked(sdev, s_step, g->allocs);
+    }
     q.retired.clear();
     if (q.ev) pool.push_back(q.ev);
     q.ev = nullptr;
@@ -335,7 +338,10 @@ void dpsnn_server::stepper_main() {
     }
     cv_done.notify_all();
     dpsnn_device sdev = dev;
-    for (auto& g : groups) free_tracked(sdev, s_step, g->allocs);
+    for (auto& g : groups) {
+        release_launch_set_host(g->L);
+        free_tracked(sdev, s_step, g->allocs);
+    }
     for (hipEvent_t ev : pool) (void)hipEventDestroy(ev);
 }
 

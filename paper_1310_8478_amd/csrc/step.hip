@@ -259,10 +259,14 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
 // target's latest stamp t_q <= t precedes the arrival at t + 1, dt = t + 1 -
 // t_q, D += A- exp(-dt / tau-).
 // ---------------------------------------------------------------------------
-template <bool FIXED, bool WINDOW, typename TgtT, int U>
+// WIN: 0 no LDS window (global atomics), 1 window over all 13 reachable
+// columns, 2 window over the own column only (targets in the neighbour
+// columns take global atomics; small LDS, several workgroups per CU).
+template <bool FIXED, int WIN, typename TgtT, int U>
 __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nds,
                                                   const uint2* __restrict__ bmap,
-                                                  uint32_t allow_age, uint32_t nparts) {
+                                                  uint32_t allow_age, uint32_t nparts,
+                                                  unsigned long long* __restrict__ set_events) {
     // block: part `part` of the column of map entry blockIdx.x / nparts
     const uint2 br = bmap[blockIdx.x / nparts];
     const uint32_t part = blockIdx.x % nparts;
@@ -285,7 +289,9 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
     __shared__ unsigned long long red64[16];
     const uint32_t BS = blockDim.x;
     const uint32_t nwin = kSlots * d.Ncol;
-    const size_t win_bytes = WINDOW ? (size_t)nwin * (FIXED ? 8 : 4) : 0;
+    constexpr bool WINDOW = WIN != 0;
+    const uint32_t nlds = WIN == 1 ? nwin : (WIN == 2 ? d.Ncol : 0u);  // window entries
+    const size_t win_bytes = (((size_t)nlds * (FIXED ? 8 : 4)) + 15) & ~(size_t)15;
     // age window: steps since each reachable target's latest spike, saturated
     // at 255 (255 also means "never" or "look it up"); staged when the
     // workgroup has enough events to reuse it
@@ -305,7 +311,7 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
     float* acc32 = (float*)acc_v;
 
     if (WINDOW) {
-        for (uint32_t x = tid; x < nwin; x += BS) {
+        for (uint32_t x = tid; x < nlds; x += BS) {
             if (FIXED) win64[x] = 0; else win32[x] = 0.0f;
         }
     }
@@ -358,7 +364,7 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
         };
         auto deliver_one = [&](bool ex, uint32_t wi, float wv, float& dv) {
             exc_events += ex ? 1u : 0u;
-            if (WINDOW) {
+            if (WIN == 1 || (WIN == 2 && wi < nlds)) {
                 if (FIXED) {
                     atomicAdd((unsigned long long*)&win64[wi],
                               (unsigned long long)(ex ? to_fixed(wv) : q_inh));
@@ -574,7 +580,7 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
                 for (int q = 0; q < U; ++q) {
                     if (!ok[q]) continue;
                     exc_events += ex_[q] ? 1u : 0u;
-                    if (WINDOW) {
+                    if (WIN == 1 || (WIN == 2 && wi[q] < nlds)) {
                         if (FIXED) {
                             atomicAdd((unsigned long long*)&win64[wi[q]],
                                       (unsigned long long)(ex_[q] ? to_fixed(wv[q]) : q_inh));
@@ -601,7 +607,7 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
     }
     if (WINDOW) {
         __syncthreads();
-        for (uint32_t x = tid; x < nwin; x += BS) {
+        for (uint32_t x = tid; x < nlds; x += BS) {
             const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
             const uint32_t kg = cmap[sl] * d.Ncol + (x - sl * d.Ncol);
             if (FIXED) {
@@ -618,6 +624,7 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
     if (tid == 0 && events) {
         atomicAdd(&stats[c & 63].events, events);
         atomicAdd(&stats[c & 63].events_exc, exc_total);
+        atomicAdd(set_events, events);
     }
 }
 
@@ -932,32 +939,41 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
     const bool fixed = L.sum_mode == DPSNN_SUM_FIXED;
     // one thread per raster word of a column and delay chunk
     const uint32_t BS = std::max<uint32_t>(tune.deliver_block, ((L.max_w + 63) / 64) * 64);
-    const size_t win = (size_t)kSlots * L.max_ncol * (fixed ? 8 : 4);
+    const size_t esz = fixed ? 8 : 4;
+    const size_t win_full = (((size_t)kSlots * L.max_ncol * esz) + 15) & ~(size_t)15;
+    const size_t win_own = (((size_t)L.max_ncol * esz) + 15) & ~(size_t)15;
     const size_t agew = (((size_t)kSlots * L.max_ncol) + 15) & ~(size_t)15;
     const size_t base = ((size_t)3 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
-    const bool use_win = tune.window && (win + base + 256 <= tune.max_lds);
-    const size_t lds0 = (use_win ? win : 0) + base;
+    // window mode: the requested one if it fits, else the own-column window
+    // if that fits, else none
+    int wmode = 0;
+    if (tune.window == 1 && win_full + base + 256 <= tune.max_lds) wmode = 1;
+    else if (tune.window >= 1 && win_own + base + 256 <= tune.max_lds) wmode = 2;
+    const size_t lds0 = (wmode == 1 ? win_full : (wmode == 2 ? win_own : 0)) + base;
     const uint32_t allow_age = (tune.age && lds0 + agew + 256 <= tune.max_lds) ? 1u : 0u;
     const size_t lds = lds0 + (allow_age ? agew : 0);
 #define DPSNN_DELIVER(FX, WN, UU)                                                              \
     do {                                                                                       \
         allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                           \
         hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(L.n_col * nparts), dim3(BS), lds, \
-                           stream, L.descs, L.bmap_col, allow_age, nparts);                    \
+                           stream, L.descs, L.bmap_col, allow_age, nparts, L.ev_count);        \
+    } while (0)
+#define DPSNN_DELIVER_W(FX, UU)                                                                \
+    do {                                                                                       \
+        if (wmode == 1) DPSNN_DELIVER(FX, 1, UU);                                              \
+        else if (wmode == 2) DPSNN_DELIVER(FX, 2, UU);                                         \
+        else DPSNN_DELIVER(FX, 0, UU);                                                         \
     } while (0)
     if (tune.unroll == 1) {
-        if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 1); else DPSNN_DELIVER(true, false, 1); }
-        else { if (use_win) DPSNN_DELIVER(false, true, 1); else DPSNN_DELIVER(false, false, 1); }
+        if (fixed) DPSNN_DELIVER_W(true, 1); else DPSNN_DELIVER_W(false, 1);
     } else if (tune.unroll == 2) {
-        if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 2); else DPSNN_DELIVER(true, false, 2); }
-        else { if (use_win) DPSNN_DELIVER(false, true, 2); else DPSNN_DELIVER(false, false, 2); }
+        if (fixed) DPSNN_DELIVER_W(true, 2); else DPSNN_DELIVER_W(false, 2);
     } else if (tune.unroll == 4) {
-        if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 4); else DPSNN_DELIVER(true, false, 4); }
-        else { if (use_win) DPSNN_DELIVER(false, true, 4); else DPSNN_DELIVER(false, false, 4); }
+        if (fixed) DPSNN_DELIVER_W(true, 4); else DPSNN_DELIVER_W(false, 4);
     } else {
-        if (fixed) { if (use_win) DPSNN_DELIVER(true, true, 8); else DPSNN_DELIVER(true, false, 8); }
-        else { if (use_win) DPSNN_DELIVER(false, true, 8); else DPSNN_DELIVER(false, false, 8); }
+        if (fixed) DPSNN_DELIVER_W(true, 8); else DPSNN_DELIVER_W(false, 8);
     }
+#undef DPSNN_DELIVER_W
 #undef DPSNN_DELIVER
     return hipGetLastError();
 }
@@ -1010,16 +1026,66 @@ void Timers::release() {
 // One step of every network of the set, in the paper's loop order: LTP,
 // delivery (+ currents and LTD), neuron update, consolidation where due, and
 // the clock tick.  Timer kinds: 0 LTP, 1 delivery, 2 neuron, 3 consolidation.
-hipError_t launch_step_set(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
+// Regime estimate of the set: fold in the last counter copy once it has
+// landed, and start a new copy every 8 steps.  A copy still in flight 16
+// steps after it was enqueued is waited for, which keeps the host at most
+// about 16 steps ahead of the device and the estimate at most that stale.
+void sample_regime(LaunchSet& L, hipStream_t stream, Net* const* members) {
+    if (!L.ev_host || !L.ev_copied) return;
+    bool landed = false;
+    if (L.copy_pending) {
+        hipError_t q = hipEventQuery(L.ev_copied);
+        if (q == hipErrorNotReady && L.steps - L.copy_steps >= 16u) q = hipEventSynchronize(L.ev_copied);
+        landed = q == hipSuccess;
+    }
+    if (landed) {
+        const unsigned long long v = *(volatile unsigned long long*)L.ev_host;
+        if (L.copy_steps > L.base_steps && L.n_col) {
+            L.per_col = (double)(v - L.base_count) / (double)(L.copy_steps - L.base_steps) /
+                        (double)L.n_col;
+            for (uint32_t k = 0; k < L.K; ++k) members[k]->per_col = L.per_col;
+        }
+        L.base_count = v;
+        L.base_steps = L.copy_steps;
+        L.copy_pending = false;
+    }
+    if (!L.copy_pending && L.steps % 8u == 0u) {
+        if (hipMemcpyAsync(L.ev_host, L.ev_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           stream) == hipSuccess &&
+            hipEventRecord(L.ev_copied, stream) == hipSuccess) {
+            L.copy_pending = true;
+            L.copy_steps = L.steps;
+        }
+    }
+}
+
+// The launch shapes for this step: explicit knobs as set, automatic ones by
+// the set's regime.  Sparse shapes (small LDS, 256-thread workgroups, several
+// per CU) pay off when each source column delivers fewer events than its
+// current window has entries and there are many columns per CU; otherwise
+// the full window and 1024-thread workgroups are faster.
+Tuning effective_tuning(const LaunchSet& L, const Tuning& tune) {
+    Tuning t = tune;
+    const bool sparse = L.n_col >= 2048u && L.per_col < L.avg_nwin;
+    if (!t.deliver_block) t.deliver_block = sparse ? 256u : 1024u;
+    if (!t.ltp_block) t.ltp_block = sparse ? 256u : 1024u;
+    if (t.window == 3u) t.window = sparse ? 2u : 1u;
+    if (t.age == 2u) t.age = sparse ? 0u : 1u;
+    if (t.ltp_stage == 2u) t.ltp_stage = sparse ? 0u : 1u;
+    return t;
+}
+
+hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipStream_t stream,
                            Net* const* members) {
     hipError_t e;
+    const Tuning tune = effective_tuning(L, tune_in);
     bool any_spikes = false;
     for (uint32_t k = 0; k < L.K; ++k) any_spikes |= members[k]->t >= 1;
     if (any_spikes) {
         const uint32_t BS = std::max<uint32_t>(tune.ltp_block, ((L.max_w + 63) / 64) * 64);
         const size_t base = ((size_t)2 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
         const size_t hw = (size_t)kSlots * L.max_ncol * sizeof(uint32_t);
-        const uint32_t allow = (base + hw <= tune.max_lds) ? 1u : 0u;
+        const uint32_t allow = (tune.ltp_stage && base + hw <= tune.max_lds) ? 1u : 0u;
         const size_t lds = base + (allow ? hw : 0);
         allow_lds(k_ltp<4>, lds);
         const uint32_t nparts = column_parts(L, tune);
@@ -1033,6 +1099,8 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune, Timers& tm, hipStre
                     : launch_deliver<uint32_t>(L, tune, stream, members, nparts);
         tm.end(stream);
         if (e != hipSuccess) return e;
+        L.steps++;
+        sample_regime(L, stream, members);
     }
     tm.begin(2, stream);
     if (L.sum_mode == DPSNN_SUM_FIXED)

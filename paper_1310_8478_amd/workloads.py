@@ -102,8 +102,17 @@ def paper_table1(k: int, **over) -> dict:
 
 
 def paper_table3(k: int, **over) -> dict:
+    """Table 3 row k.  The paper does not say how synaptic strengths change
+    with M; here every synaptic quantity (initial, inhibitory and maximum
+    weight, STDP amplitudes, consolidation bias) is scaled by 200 / M, which
+    keeps a neuron's total synaptic drive at that of the M = 200 networks, and
+    the thalamic drive per neuron is that of the Table 1 runs."""
     M, ncol, gx, gy = PAPER_TABLE3[k][:4]
-    base = dict(thalamic_rate=float(np.float32(PAPER_DRIVE_PER_NEURON * ncol)))
+    sc = 200.0 / M
+    f = lambda x: float(np.float32(x))  # noqa: E731
+    base = dict(thalamic_rate=f(PAPER_DRIVE_PER_NEURON * ncol),
+                w_exc_init=f(6.0 * sc), w_inh=f(-5.0 * sc), w_max=f(10.0 * sc),
+                a_plus=f(0.1 * sc), a_minus=f(0.12 * sc), wu_bias=f(0.01 * sc))
     base.update(over)
     return paper_shaped(grid=(gx, gy), M=M, neurons_per_column=ncol, **base)
 

@@ -201,6 +201,7 @@ def test_high_thalamic_rate_bitexact(dp, orc, mode):
 TUNINGS = [
     ((0, 256),), ((0, 512), (3, 1)), ((2, 0),), ((3, 2), (1, 1024)), ((2, 0), (0, 256), (3, 1)),
     ((5, 1),), ((5, 3),), ((5, 7), (2, 0)), ((5, 64), (0, 256), (1, 512)),
+    ((2, 2),), ((2, 2), (6, 0), (0, 512), (1, 256)), ((2, 2), (5, 5), (3, 4)), ((6, 0),),
 ]
 
 
@@ -212,8 +213,8 @@ def test_dense_regime_column_parts(dp):
     _say("dense regime, column parts 1 vs 13 vs 200")
     ref = gpu_run(dp, cfg, T, tuning=((5, 1),), conn=False)
     assert (np.bincount(ref["tt"], minlength=T + 1)[110:] == 2500).sum() >= 20
-    for p in (13, 200):
-        g = gpu_run(dp, cfg, T, tuning=((5, p),), conn=False)
+    for tn in (((5, 13),), ((5, 200),), ((5, 9), (2, 2), (6, 0))):
+        g = gpu_run(dp, cfg, T, tuning=tn, conn=False)
         assert_bitexact(g, ref, conn=False)
         assert g["stats"]["events"] == ref["stats"]["events"]
         assert g["stats"]["ltp_visits"] == ref["stats"]["ltp_visits"]
