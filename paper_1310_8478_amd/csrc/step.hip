@@ -870,6 +870,11 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
 // Consolidation: for every excitatory synapse (reverse entry x, forward
 // position f): sd = P - D; w <- clamp(w + (bias + sd), 0, w_max);
 // P <- decay * sd; D <- 0.
+// Done in two passes so that only one array is touched out of order:
+//   k_wupdate     (reverse order): sd = P - D[f]; D[f] <- sd; P <- decay * sd;
+//   k_wupdate_fwd (forward order, coalesced): w <- clamp(w + (bias + D)); D <- 0
+// for the excitatory positions (the inhibitory synapses of a column are one
+// delay-1 range of its forward block, which the second pass skips).
 __global__ __launch_bounds__(256) void k_wupdate(const NetDesc* __restrict__ nds,
                                                  const uint2* __restrict__ bmap) {
     const uint2 br = bmap[blockIdx.x];
@@ -877,19 +882,44 @@ __global__ __launch_bounds__(256) void k_wupdate(const NetDesc* __restrict__ nds
     const uint32_t* __restrict__ rev_fwd = nd.rev_fwd;
     float* __restrict__ P = nd.Pacc;
     float* __restrict__ Dacc = nd.Dacc;
-    float* __restrict__ w = (float*)nd.w;
-    const float bias = nd.wu_bias, decay = nd.sd_decay, wmax = nd.w_max;
+    const float decay = nd.sd_decay;
     const unsigned long long chunk = (unsigned long long)blockDim.x * kWupdateItems;
     const unsigned long long x0 = (unsigned long long)br.y * chunk;
     const unsigned long long x1 = min(x0 + chunk, nd.S_exc);
     for (unsigned long long x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
         const uint32_t f = rev_fwd[x];
         const float sd = P[x] - Dacc[f];
-        float nw = w[f] + (bias + sd);
+        Dacc[f] = sd;
+        P[x] = decay * sd;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wupdate_fwd(const NetDesc* __restrict__ nds) {
+    const NetDesc& nd = *nds;
+    const Dims d = nd.d;
+    const uint32_t* __restrict__ seg_off = nd.seg_off;
+    float* __restrict__ Dacc = nd.Dacc;
+    float* __restrict__ w = (float*)nd.w;
+    const float bias = nd.wu_bias, wmax = nd.w_max;
+    const uint64_t S = (uint64_t)d.N * d.M;
+    const uint64_t colsz = (uint64_t)d.Ncol * d.M;
+    const uint64_t chunk = (uint64_t)blockDim.x * kWupdateItems;
+    const uint64_t f0 = (uint64_t)blockIdx.x * chunk;
+    const uint64_t f1 = min(f0 + chunk, S);
+    uint32_t cur = 0xFFFFFFFFu, lo = 0, hi = 0;  // inhibitory range of column cur
+    for (uint64_t f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
+        const uint32_t c = (uint32_t)(f / colsz);
+        if (c != cur) {
+            cur = c;
+            const size_t s1 = (size_t)c * d.segs;
+            lo = d.Ne < d.Ncol ? seg_off[s1 + d.Ne] : 0u;
+            hi = d.Ne < d.Ncol ? seg_off[s1 + d.Ncol] : 0u;
+        }
+        if (f >= lo && f < hi) continue;
+        float nw = w[f] + (bias + Dacc[f]);
         if (nw < 0.0f) nw = 0.0f;
         if (nw > wmax) nw = wmax;
         w[f] = nw;
-        P[x] = decay * sd;
         Dacc[f] = 0.0f;
     }
 }
@@ -1117,6 +1147,8 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipS
         if (Tw && (n.t + 1) % Tw == 0 && n.S_exc && L.n_wu[k]) {
             tm.begin(3, stream);
             hipLaunchKernelGGL(k_wupdate, dim3(L.n_wu[k]), dim3(256), 0, stream, L.descs + k, L.bmap_wu[k]);
+            const uint64_t nfwd = ((uint64_t)n.S + 256ull * kWupdateItems - 1) / (256ull * kWupdateItems);
+            hipLaunchKernelGGL(k_wupdate_fwd, dim3((uint32_t)nfwd), dim3(256), 0, stream, L.descs + k);
             tm.end(stream);
             n.consolidations++;
             if ((e = hipGetLastError()) != hipSuccess) return e;
