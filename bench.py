@@ -366,7 +366,6 @@ def bench_paper(args, mode):
             if done % 2000 == 0:
                 print(f"[bench] paper {label}: warm-up {done}/{args.paper_warmup}",
                       file=sys.stderr, flush=True)
-        net.set_timing(True)
         s0 = net.stats()
         t0 = time.perf_counter()
         done = 0
@@ -377,8 +376,14 @@ def bench_paper(args, mode):
         net.sync()
         wall = time.perf_counter() - t0
         s1 = net.stats()
+        # per-kernel breakdown over the next 200 steps, with the timers on
+        net.set_timing(True)
+        net.step(200)
+        net.sync()
+        s2 = net.stats()
         net.close()
         d = {k: s1[k] - s0[k] for k in s1}
+        kt = {k: (s2[f"ms_{k}"] - s1[f"ms_{k}"]) / 200.0 for k in KERNELS}
         sim_s = args.paper_steps / 1000.0
         rate = d["spikes"] / N / sim_s
         wps = wall / sim_s
@@ -387,7 +392,7 @@ def bench_paper(args, mode):
         return {"synapses": S, "neurons": N, "rate_hz": rate, "wall_s_per_sim_s": wps,
                 "normalized_s": wps / (rate * S) if rate > 0 else None,
                 "events_per_s": d["events"] / wall, "build_s": build_s,
-                "kernel_ms_per_step": {k: d[f"ms_{k}"] / args.paper_steps for k in KERNELS}}
+                "kernel_ms_per_step": kt}
 
     t1 = []
     for k, (gx, gy, rate, wps, norm) in enumerate(W.PAPER_TABLE1):
@@ -514,6 +519,14 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s1 = net.stats()
+    # the per-kernel timers add a few events per step; the same steps again
+    # without them give the step time a caller sees (matters at small sizes)
+    net.set_timing(False)
+    n_plain = min(args.steps, 500)
+    t0 = time.perf_counter()
+    net.step(n_plain)
+    net.sync()
+    ms_plain = 1000.0 * (time.perf_counter() - t0) / n_plain
     net.close()
 
     d = {k: s1[k] - s0[k] for k in s1 if isinstance(s1[k], (int, float))}
@@ -570,6 +583,7 @@ def main():
             "neurons": N, "synapses": N * M, "sum_mode": args.mode,
             "timed_steps": f"{args.warmup}..{args.warmup + args.steps - 1}",
         },
+        "ms_per_step_without_timers": ms_plain,
         "wall_s_per_sim_s_per_hz": (wall / sim_s) / rate_hz if rate_hz > 0 else None,
         "wall_s_per_sim_s": wall / sim_s,
         "rate_hz": rate_hz,

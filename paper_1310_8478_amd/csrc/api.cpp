@@ -120,7 +120,6 @@ std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
         sizeof(uint64_t) * (size_t)d.R * d.C * d.W,       // ring
         sizeof(DevStats) * 64,                            // stats
         sizeof(uint32_t) * (N / 1024 + 2),                // scan_tmp
-        sizeof(uint32_t) * 4,                             // t_dev
     };
     if (c->sum_mode == DPSNN_SUM_ORDERED) {
         b.push_back(sizeof(uint32_t) * N);                // ev_cnt
@@ -436,7 +435,7 @@ NetDesc Net::make_desc() const {
     NetDesc nd;
     std::memset(&nd, 0, sizeof(nd));
     nd.d = d;
-    nd.t_ptr = t_dev;
+    nd.t0 = t;
     nd.colmap = colmap; nd.srcmap = srcmap; nd.seg_off = seg_off; nd.tgt = tgt;
     nd.w = w; nd.Dacc = Dacc; nd.rowptr = rowptr; nd.rev_srcd = rev_srcd; nd.rev_fwd = rev_fwd;
     nd.Pacc = Pacc; nd.v = v; nd.u = u; nd.acc = acc; nd.hist = hist; nd.t_old = t_old;
@@ -567,7 +566,6 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     n->v = (float*)p[k++]; n->u = (float*)p[k++]; n->acc = p[k++];
     n->hist = (uint32_t*)p[k++]; n->t_old = (int32_t*)p[k++]; n->t_last = (int32_t*)p[k++];
     n->ring = (uint64_t*)p[k++]; n->stats = (DevStats*)p[k++]; n->scan_tmp = (uint32_t*)p[k++];
-    n->t_dev = (uint32_t*)p[k++];
     if (cfg->sum_mode == DPSNN_SUM_ORDERED) {
         n->ev_cnt = (uint32_t*)p[k++]; n->ev_start = (uint32_t*)p[k++];
         n->ev_key = (unsigned long long*)p[k++]; n->ev_w = (float*)p[k++];
@@ -623,7 +621,6 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     DPSNN_TRY_HIP(hipMemsetAsync(n->acc, 0, accb, n->stream));
     DPSNN_TRY_HIP(hipMemsetAsync(n->ring, 0, sizeof(uint64_t) * (size_t)dv.R * dv.C * dv.W, n->stream));
     DPSNN_TRY_HIP(hipMemsetAsync(n->stats, 0, sizeof(DevStats) * 64, n->stream));
-    DPSNN_TRY_HIP(hipMemsetAsync(n->t_dev, 0, sizeof(uint32_t) * 4, n->stream));
     if (n->ev_cnt) {
         DPSNN_TRY_HIP(hipMemsetAsync(n->ev_cnt, 0, sizeof(uint32_t) * dv.N, n->stream));
         DPSNN_TRY_HIP(hipMemsetAsync(n->ev_start, 0, sizeof(uint32_t) * (dv.N + 1), n->stream));

@@ -44,7 +44,7 @@ struct DevStats {
 // maps each workgroup to (network, column or word) through a block table.
 struct NetDesc {
     Dims d;
-    uint32_t* t_ptr;                 // steps completed (device-resident clock)
+    uint32_t t0;                     // steps completed when the launch set was made
     const uint32_t* colmap;          // [C*13]
     const uint32_t* srcmap;          // [C*13]
     const uint32_t* seg_off;         // [C*segs + 1]

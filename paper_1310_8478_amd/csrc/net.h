@@ -99,7 +99,6 @@ struct Net {
     struct Alloc { void* p; size_t bytes; };
     std::vector<Alloc> allocs;
 
-    uint32_t* t_dev = nullptr;    // device clock
     uint32_t* colmap = nullptr;   // [C*13] column reached from c through slot q
     uint32_t* srcmap = nullptr;   // [C*13] column that reaches c through slot q
     uint32_t* seg_off = nullptr;  // [C*segs + 1]

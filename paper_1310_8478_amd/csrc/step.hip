@@ -3,16 +3,18 @@
 // plasticity" block of Table 2).
 //
 //   k_ltp      item 2.1: every neuron stamped t potentiates its incoming
-//              excitatory synapses; one workgroup per target column walks the
+//              excitatory synapses; workgroups per target column walk the
 //              reverse rows of the column's spiking neurons (contiguous runs).
-//   k_deliver  items 2.3-2.6: one workgroup per source column delivers the
+//   k_deliver  items 2.3-2.6: workgroups per source column deliver the
 //              spikes stamped t-d+1 through the column's delay-d synapses,
-//              accumulates the currents of the 13 reachable target columns
-//              in an LDS window, applies LTD, then flushes the window.
+//              accumulate the currents of the reachable target columns in an
+//              LDS window, apply LTD, then flush the window.
 //   k_neuron   item 2.7 plus the thalamic input: Izhikevich update with two
-//              0.5 ms sub-steps, threshold and reset, spike history, and the
-//              raster word of each wavefront written with one ballot.
-//   k_wupdate  every weight_update_period steps: fold P - D into the weights.
+//              0.5 ms sub-steps, threshold and reset, spike history, the
+//              raster word of each wavefront written with one ballot, and
+//              the clock advanced by the network's last workgroup.
+//   k_wupdate, k_wupdate_fwd  every weight_update_period steps: fold P - D
+//              into the weights.
 #include "net.h"
 
 namespace dpsnn {
@@ -29,13 +31,13 @@ namespace {
 template <int U>
 __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
                                               const uint2* __restrict__ bmap, uint32_t allow_stage,
-                                              uint32_t nparts) {
+                                              uint32_t nparts, uint32_t tstep) {
     // block: part `part` of the column of map entry blockIdx.x / nparts
     const uint2 br = bmap[blockIdx.x / nparts];
     const uint32_t part = blockIdx.x % nparts;
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
-    const uint32_t t = *nd.t_ptr;
+    const uint32_t t = nd.t0 + tstep;
     if (t < 1) return;  // no stamp 0: nothing to potentiate in the first step
     const uint64_t* __restrict__ ring = nd.ring;
     const uint32_t* __restrict__ hist = nd.hist;
@@ -266,13 +268,14 @@ template <bool FIXED, int WIN, typename TgtT, int U>
 __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nds,
                                                   const uint2* __restrict__ bmap,
                                                   uint32_t allow_age, uint32_t nparts,
-                                                  unsigned long long* __restrict__ set_events) {
+                                                  unsigned long long* __restrict__ set_events,
+                                                  uint32_t tstep) {
     // block: part `part` of the column of map entry blockIdx.x / nparts
     const uint2 br = bmap[blockIdx.x / nparts];
     const uint32_t part = blockIdx.x % nparts;
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
-    const uint32_t t = *nd.t_ptr;
+    const uint32_t t = nd.t0 + tstep;
     if (t < 1) return;  // no spike has been stamped yet
     const uint64_t* __restrict__ ring = nd.ring;
     const uint32_t* __restrict__ seg_off = nd.seg_off;
@@ -636,11 +639,12 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
 // ---------------------------------------------------------------------------
 template <int PASS, typename TgtT>
 __global__ __launch_bounds__(256) void k_deliver_seq(const NetDesc* __restrict__ nds,
-                                                     const uint2* __restrict__ bmap) {
+                                                     const uint2* __restrict__ bmap,
+                                                     uint32_t tstep) {
     const uint2 br = bmap[blockIdx.x];
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
-    const uint32_t t = *nd.t_ptr;
+    const uint32_t t = nd.t0 + tstep;
     if (t < 1) return;
     const uint64_t* __restrict__ ring = nd.ring;
     const uint32_t* __restrict__ seg_off = nd.seg_off;
@@ -718,11 +722,11 @@ __global__ __launch_bounds__(256) void k_deliver_seq(const NetDesc* __restrict__
 // ---------------------------------------------------------------------------
 template <uint32_t MODE>
 __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
-                                                const uint2* __restrict__ bmap) {
+                                                const uint2* __restrict__ bmap, uint32_t tstep) {
     const uint2 br = bmap[blockIdx.x];
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
-    const uint32_t t = *nd.t_ptr;
+    const uint32_t t = nd.t0 + tstep;
     float* __restrict__ v = nd.v;
     float* __restrict__ u = nd.u;
     void* __restrict__ acc_v = nd.acc;
@@ -924,11 +928,6 @@ __global__ __launch_bounds__(256) void k_wupdate_fwd(const NetDesc* __restrict__
     }
 }
 
-// Advance the clock of every network of a launch set by one step.
-__global__ void k_tick(const NetDesc* __restrict__ nds, uint32_t n) {
-    for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) *nds[k].t_ptr += 1u;
-}
-
 template <typename K>
 void allow_lds(K kernel, size_t bytes) {
     if (bytes > 65536)
@@ -952,18 +951,18 @@ uint32_t column_parts(const LaunchSet& L, const Tuning& tune) {
 
 template <typename TgtT>
 hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, Net* const* members,
-                          uint32_t nparts) {
+                          uint32_t nparts, uint32_t tstep) {
     if (L.sum_mode == DPSNN_SUM_ORDERED) {
         // one network only (checked when the set is made)
         Net& n = *members[0];
         hipLaunchKernelGGL((k_deliver_seq<0, TgtT>), dim3(L.n_col), dim3(256), 0, stream, L.descs,
-                           L.bmap_col);
+                           L.bmap_col, tstep);
         if (n.t >= 1) {
             hipError_t e = scan_u32(n, stream, n.ev_cnt, n.ev_start, n.d.N);
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL((k_deliver_seq<1, TgtT>), dim3(L.n_col), dim3(256), 0, stream, L.descs,
-                           L.bmap_col);
+                           L.bmap_col, tstep);
         return hipGetLastError();
     }
     const bool fixed = L.sum_mode == DPSNN_SUM_FIXED;
@@ -986,7 +985,7 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
     do {                                                                                       \
         allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                           \
         hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(L.n_col * nparts), dim3(BS), lds, \
-                           stream, L.descs, L.bmap_col, allow_age, nparts, L.ev_count);        \
+                           stream, L.descs, L.bmap_col, allow_age, nparts, L.ev_count, tstep); \
     } while (0)
 #define DPSNN_DELIVER_W(FX, UU)                                                                \
     do {                                                                                       \
@@ -1053,15 +1052,13 @@ void Timers::release() {
     pool.clear();
 }
 
-// One step of every network of the set, in the paper's loop order: LTP,
-// delivery (+ currents and LTD), neuron update, consolidation where due, and
-// the clock tick.  Timer kinds: 0 LTP, 1 delivery, 2 neuron, 3 consolidation.
 // Regime estimate of the set: fold in the last counter copy once it has
 // landed, and start a new copy every 8 steps.  A copy still in flight 16
 // steps after it was enqueued is waited for, which keeps the host at most
 // about 16 steps ahead of the device and the estimate at most that stale.
 void sample_regime(LaunchSet& L, hipStream_t stream, Net* const* members) {
-    if (!L.ev_host || !L.ev_copied) return;
+    // sets under 2048 columns always take the dense shapes: nothing to measure
+    if (!L.ev_host || !L.ev_copied || L.n_col < 2048u) return;
     bool landed = false;
     if (L.copy_pending) {
         hipError_t q = hipEventQuery(L.ev_copied);
@@ -1105,10 +1102,19 @@ Tuning effective_tuning(const LaunchSet& L, const Tuning& tune) {
     return t;
 }
 
+// One step of every network of the set, in the paper's loop order: LTP,
+// delivery (+ currents and LTD), neuron update, consolidation where due, and
+// the clock advance.  Timer kinds: 0 LTP, 1 delivery, 2 neuron, 3 consolidation.
 hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipStream_t stream,
                            Net* const* members) {
     hipError_t e;
     const Tuning tune = effective_tuning(L, tune_in);
+    // every member has advanced by the same number of steps since the set was
+    // made; the kernels read t = t0 + tstep
+    if (L.K == 0) return hipSuccess;
+    const uint32_t tstep = members[0]->t - L.host_descs[0].t0;
+    for (uint32_t k = 1; k < L.K; ++k)
+        if (members[k]->t - L.host_descs[k].t0 != tstep) return hipErrorInvalidValue;
     bool any_spikes = false;
     for (uint32_t k = 0; k < L.K; ++k) any_spikes |= members[k]->t >= 1;
     if (any_spikes) {
@@ -1121,12 +1127,12 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipS
         const uint32_t nparts = column_parts(L, tune);
         tm.begin(0, stream);
         hipLaunchKernelGGL(k_ltp<4>, dim3(L.n_col * nparts), dim3(BS), lds, stream, L.descs,
-                           L.bmap_col, allow, nparts);
+                           L.bmap_col, allow, nparts, tstep);
         tm.end(stream);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         tm.begin(1, stream);
-        e = L.tgt16 ? launch_deliver<uint16_t>(L, tune, stream, members, nparts)
-                    : launch_deliver<uint32_t>(L, tune, stream, members, nparts);
+        e = L.tgt16 ? launch_deliver<uint16_t>(L, tune, stream, members, nparts, tstep)
+                    : launch_deliver<uint32_t>(L, tune, stream, members, nparts, tstep);
         tm.end(stream);
         if (e != hipSuccess) return e;
         L.steps++;
@@ -1134,11 +1140,11 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipS
     }
     tm.begin(2, stream);
     if (L.sum_mode == DPSNN_SUM_FIXED)
-        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_FIXED>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu);
+        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_FIXED>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu, tstep);
     else if (L.sum_mode == DPSNN_SUM_ATOMIC)
-        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_ATOMIC>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu);
+        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_ATOMIC>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu, tstep);
     else
-        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_ORDERED>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu);
+        hipLaunchKernelGGL(k_neuron<DPSNN_SUM_ORDERED>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu, tstep);
     tm.end(stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (uint32_t k = 0; k < L.K; ++k) {
@@ -1154,8 +1160,6 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipS
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
-    hipLaunchKernelGGL(k_tick, dim3(1), dim3(256), 0, stream, L.descs, L.K);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     for (uint32_t k = 0; k < L.K; ++k) members[k]->t += 1;
     return hipSuccess;
 }
