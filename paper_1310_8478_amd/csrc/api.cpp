@@ -101,7 +101,9 @@ int validate(const dpsnn_config* c, Derived* o) {
 
 // Byte sizes of every device array, in allocation order.
 std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
-    const size_t N = d.N, S = d.S, Se = d.S_exc;
+    // per-synapse arrays are padded to whole 4-element quads: the kernels read
+    // aligned quads that may extend past the last synapse
+    const size_t N = d.N, S = (d.S + 3) & ~(size_t)3, Se = (d.S_exc + 3) & ~(size_t)3;
     std::vector<size_t> b = {
         sizeof(uint32_t) * d.C * kSlots,                  // colmap
         sizeof(uint32_t) * d.C * kSlots,                  // srcmap

@@ -21,7 +21,7 @@ struct Tuning {
     uint32_t deliver_block = 0;   // 256, 512, 1024; 0 auto (sparse 256, dense 1024)
     uint32_t ltp_block = 0;       // 256, 512, 1024; 0 auto (sparse 256, dense 1024)
     uint32_t window = 3;          // 0 off, 1 all 13 columns, 2 own column; 3 auto (2 / 1)
-    uint32_t unroll = 8;
+    uint32_t unroll = 4;           // events (quads) in flight per lane in delivery
     uint32_t age = 2;             // LDS target spike ages: 0 off, 1 on, 2 auto (off / on)
     uint32_t parts = 0;           // workgroups per column (0: chosen per launch set)
     uint32_t ltp_stage = 2;       // LDS source spike history in LTP: 0, 1, 2 auto (0 / 1)

@@ -324,8 +324,50 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
 
     const long long q_inh = to_fixed(d.w_inh);
     const uint32_t split = (d.Ne > 0 && d.Ne < d.Ncol) ? d.Ne : 0u;
-    unsigned long long events = 0, exc_events = 0;
+    unsigned long long ev_local = 0, exc_events = 0;  // this thread's deliveries
     bool staged = false;
+    // the column's inhibitory synapses (all of delay 1) form one forward range
+    const size_t s1 = (size_t)c * d.segs;
+    const uint32_t inh_lo = d.Ne < d.Ncol ? seg_off[s1 + d.Ne] : 0u;
+    const uint32_t inh_hi = d.Ne < d.Ncol ? seg_off[s1 + d.Ncol] : 0u;
+    auto is_exc = [&](uint32_t p) { return !(p >= inh_lo && p < inh_hi); };
+    auto global_id = [&](uint32_t wi) {
+        const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, wi) : wi / d.Ncol;
+        return cmap[sl] * d.Ncol + (wi - sl * d.Ncol);
+    };
+    // one delivery to window index wi with weight wv (excitatory: ex), and
+    // its LTD added to dv
+    auto deliver_one = [&](bool ex, uint32_t wi, float wv, float& dv) {
+        ++ev_local;
+        exc_events += ex ? 1u : 0u;
+        if (WIN == 1 || (WIN == 2 && wi < nlds)) {
+            if (FIXED) {
+                atomicAdd((unsigned long long*)&win64[wi],
+                          (unsigned long long)(ex ? to_fixed(wv) : q_inh));
+            } else {
+                atomicAdd(&win32[wi], ex ? wv : d.w_inh);
+            }
+        } else {
+            if (FIXED) {
+                atomicAdd((unsigned long long*)&acc64[global_id(wi)],
+                          (unsigned long long)(ex ? to_fixed(wv) : q_inh));
+            } else {
+                atomicAdd(&acc32[global_id(wi)], ex ? wv : d.w_inh);
+            }
+        }
+        if (ex) {
+            const uint32_t ag = staged ? age[wi] : 255u;
+            uint32_t dt = 0xFFFFFFFFu;
+            if (ag < 255u) {
+                dt = ag + 1u;
+            } else {
+                const int32_t tq = t_last[global_id(wi)];
+                if (tq != kNoSpike) dt = (uint32_t)((int64_t)t + 1 - tq);
+            }
+            if (dt != 0xFFFFFFFFu)
+                dv = dv + (dt < 64u ? tmh[dt] : (dt < tm_len ? tm[dt] : 0.0f));
+        }
+    };
 
     // Dense case: every neuron of the column fired in each of the last Dmax
     // steps, so every synapse of the column delivers and the events are the
@@ -346,10 +388,6 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
         const uint32_t c0 = c * d.Ncol * d.M;
         const uint32_t cb = part_bound4(c0, c0 + d.Ncol * d.M, part, nparts);
         const uint32_t total = part_bound4(c0, c0 + d.Ncol * d.M, part + 1u, nparts) - cb;
-        const size_t s1 = (size_t)c * d.segs;
-        // inhibitory synapses all have delay 1: one range of the d = 1 block
-        const uint32_t inh_lo = d.Ne < d.Ncol ? seg_off[s1 + d.Ne] : cb;
-        const uint32_t inh_hi = d.Ne < d.Ncol ? seg_off[s1 + d.Ncol] : cb;
         if (allow_age && total >= nwin) {  // block-uniform
             for (uint32_t x = tid; x < nwin; x += BS) {
                 const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
@@ -360,42 +398,6 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
             staged = true;
         }
         __syncthreads();
-        // one delivery through forward position p (excitatory flag ex)
-        auto global_id = [&](uint32_t wi) {
-            const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, wi) : wi / d.Ncol;
-            return cmap[sl] * d.Ncol + (wi - sl * d.Ncol);
-        };
-        auto deliver_one = [&](bool ex, uint32_t wi, float wv, float& dv) {
-            exc_events += ex ? 1u : 0u;
-            if (WIN == 1 || (WIN == 2 && wi < nlds)) {
-                if (FIXED) {
-                    atomicAdd((unsigned long long*)&win64[wi],
-                              (unsigned long long)(ex ? to_fixed(wv) : q_inh));
-                } else {
-                    atomicAdd(&win32[wi], ex ? wv : d.w_inh);
-                }
-            } else {
-                if (FIXED) {
-                    atomicAdd((unsigned long long*)&acc64[global_id(wi)],
-                              (unsigned long long)(ex ? to_fixed(wv) : q_inh));
-                } else {
-                    atomicAdd(&acc32[global_id(wi)], ex ? wv : d.w_inh);
-                }
-            }
-            if (ex) {
-                const uint32_t ag = staged ? age[wi] : 255u;
-                uint32_t dt = 0xFFFFFFFFu;
-                if (ag < 255u) {
-                    dt = ag + 1u;
-                } else {
-                    const int32_t tq = t_last[global_id(wi)];
-                    if (tq != kNoSpike) dt = (uint32_t)((int64_t)t + 1 - tq);
-                }
-                if (dt != 0xFFFFFFFFu)
-                    dv = dv + (dt < 64u ? tmh[dt] : (dt < tm_len ? tm[dt] : 0.0f));
-            }
-        };
-        auto is_exc = [&](uint32_t p) { return !(p >= inh_lo && p < inh_hi); };
         // unaligned head and tail (at most 3 positions each), one lane each
         const uint32_t fin = cb + total;
         const uint32_t a0 = min(fin, (cb + 3u) & ~3u);
@@ -472,7 +474,6 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
             if (na < wr_.end) load(na, A);
             if (nb < wr_.end) process(B);
         }
-        events = (tid == 0) ? total : 0u;
     }
 
     // tasks (delay, raster word), processed a whole number of delays at a
@@ -517,27 +518,28 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
             }
             __syncthreads();
             const uint32_t nr = min(BS, nruns - r0);
-            uint32_t a = 0, len = 0, isx = 0;
+            // run -> its forward range [a, e) and the aligned quads over it
+            uint32_t a = 0, e = 0, nq = 0;
             if (tid < nr) {
                 const uint32_t le = min(pref[tid], d.Ncol);
                 const uint32_t ls = min(pos0[tid], le);
                 const uint32_t rd = min(max(excf[tid], 1u), d.Dmax);
                 const size_t sb = (size_t)c * d.segs + (size_t)(rd - 1u) * d.Ncol;
                 a = seg_off[sb + ls];
-                len = seg_off[sb + le] - a;
-                isx = ls < d.Ne ? 1u : 0u;
+                e = max(a, seg_off[sb + le]);
+                nq = e > a ? ((e + 3u) >> 2) - (a >> 2) : 0u;
             }
             __syncthreads();
-            uint32_t E;
-            const uint32_t ex = block_scan(len, sh, E);
+            uint32_t Q;
+            const uint32_t qx = block_scan(nq, sh, Q);
             if (tid < nr) {
                 pos0[tid] = a;
-                excf[tid] = isx;
-                pref[tid] = ex;
+                excf[tid] = e;
+                pref[tid] = qx;
             }
-            uint32_t plo, phi;
-            part_slice(E, part, nparts, plo, phi);
-            if (allow_age && !staged && phi - plo >= nwin) {  // block-uniform
+            uint32_t qlo, qhi;
+            part_slice(Q, part, nparts, qlo, qhi);
+            if (allow_age && !staged && 4u * (qhi - qlo) >= nwin) {  // block-uniform
                 for (uint32_t x = tid; x < nwin; x += BS) {
                     const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
                     const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
@@ -547,64 +549,68 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
                 staged = true;
             }
             __syncthreads();
-            const WaveRange wr_ = wave_range_in(plo, phi);
+            // each lane takes one quad of positions p .. p+3 of a run at a time
+            // (vector loads; bit j of the mask: p + j lies in the run)
+            constexpr int QU = U >= 2 ? U / 2 : 1;
+            const WaveRange wr_ = wave_range_in(qlo, qhi);
             uint32_t cur = wr_.begin < wr_.end ? upper_run(pref, 0u, nr, wr_.begin) : 0u;
-            for (uint32_t eb = wr_.begin; eb < wr_.end; eb += 64u * U) {
-                uint32_t pos[U], wi[U];
-                bool ok[U], ex_[U];
-                float wv[U], dv[U];
-                int32_t tl[U];
-                uint32_t kg[U];
+            for (uint32_t kb = wr_.begin; kb < wr_.end; kb += 64u * QU) {
+                uint32_t p4[QU], m4[QU], ti[QU][4];
+                bool ex4[QU];
+                float4 wv[QU], dv[QU];
 #pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const uint32_t sb = eb + q * 64u;
-                    const uint32_t e = sb + lane_id();
-                    ok[q] = e < wr_.end;
+                for (int q = 0; q < QU; ++q) {
+                    const uint32_t sb = kb + q * 64u;
+                    const uint32_t k = sb + lane_id();
+                    const bool ok = k < wr_.end;
                     if (sb < wr_.end && cur + 1 < nr && pref[cur + 1] <= sb)
                         cur = upper_run(pref, cur + 1, nr, sb);
-                    const uint32_t r = ok[q] ? lane_run(pref, cur, nr, e) : 0u;
-                    pos[q] = ok[q] ? pos0[r] + (e - pref[r]) : 0u;
-                    ex_[q] = ok[q] && excf[r];
-                }
-                for (int q = 0; q < U; ++q) {
-                    wi[q] = ok[q] ? (uint32_t)tgt[pos[q]] : 0u;
-                    wv[q] = ex_[q] ? w[pos[q]] : d.w_inh;
-                    dv[q] = ex_[q] ? Dacc[pos[q]] : 0.0f;
+                    const uint32_t r = ok ? lane_run(pref, cur, nr, k) : 0u;
+                    const uint32_t ra = pos0[r], re = excf[r];
+                    const uint32_t p = ok ? ((ra >> 2) + (k - pref[r])) << 2 : 0u;
+                    uint32_t m = 0;
+#pragma unroll
+                    for (uint32_t j = 0; j < 4; ++j) m |= (ok && p + j >= ra && p + j < re) ? (1u << j) : 0u;
+                    p4[q] = p;
+                    m4[q] = m;
+                    ex4[q] = m && is_exc(ra);
                 }
 #pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, wi[q]) : wi[q] / d.Ncol;
-                    kg[q] = cmap[sl] * d.Ncol + (wi[q] - sl * d.Ncol);
-                    const uint32_t ag = (staged && ex_[q]) ? age[wi[q]] : 255u;
-                    tl[q] = !ex_[q] ? kNoSpike
-                                    : (ag < 255u ? (int32_t)(t - ag) : t_last[kg[q]]);
-                }
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    if (!ok[q]) continue;
-                    exc_events += ex_[q] ? 1u : 0u;
-                    if (WIN == 1 || (WIN == 2 && wi[q] < nlds)) {
-                        if (FIXED) {
-                            atomicAdd((unsigned long long*)&win64[wi[q]],
-                                      (unsigned long long)(ex_[q] ? to_fixed(wv[q]) : q_inh));
-                        } else {
-                            atomicAdd(&win32[wi[q]], wv[q]);
-                        }
+                for (int q = 0; q < QU; ++q) {
+                    if (sizeof(TgtT) == 2) {
+                        const uint2 tv = m4[q] ? *(const uint2*)(tgt + p4[q]) : make_uint2(0u, 0u);
+                        ti[q][0] = tv.x & 0xFFFFu; ti[q][1] = tv.x >> 16;
+                        ti[q][2] = tv.y & 0xFFFFu; ti[q][3] = tv.y >> 16;
                     } else {
-                        if (FIXED) {
-                            atomicAdd((unsigned long long*)&acc64[kg[q]],
-                                      (unsigned long long)(ex_[q] ? to_fixed(wv[q]) : q_inh));
-                        } else {
-                            atomicAdd(&acc32[kg[q]], wv[q]);
-                        }
+                        const uint4 tv = m4[q] ? *(const uint4*)((const uint32_t*)tgt + p4[q])
+                                               : make_uint4(0u, 0u, 0u, 0u);
+                        ti[q][0] = tv.x; ti[q][1] = tv.y; ti[q][2] = tv.z; ti[q][3] = tv.w;
                     }
-                    if (tl[q] != kNoSpike) {
-                        const uint32_t dt = (uint32_t)((int64_t)t + 1 - tl[q]);
-                        Dacc[pos[q]] = dv[q] + (dt < 64u ? tmh[dt] : (dt < tm_len ? tm[dt] : 0.0f));
+                    wv[q] = ex4[q] ? *(const float4*)(w + p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    dv[q] = ex4[q] ? *(const float4*)(Dacc + p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+#pragma unroll
+                for (int q = 0; q < QU; ++q) {
+                    const uint32_t m = m4[q];
+                    if (!m) continue;
+                    const bool ex = ex4[q];
+                    if (m & 1u) deliver_one(ex, ti[q][0], wv[q].x, dv[q].x);
+                    if (m & 2u) deliver_one(ex, ti[q][1], wv[q].y, dv[q].y);
+                    if (m & 4u) deliver_one(ex, ti[q][2], wv[q].z, dv[q].z);
+                    if (m & 8u) deliver_one(ex, ti[q][3], wv[q].w, dv[q].w);
+                    if (ex) {
+                        // a partial quad may share positions with another run
+                        if (m == 0xFu) {
+                            *(float4*)(Dacc + p4[q]) = dv[q];
+                        } else {
+                            if (m & 1u) Dacc[p4[q]] = dv[q].x;
+                            if (m & 2u) Dacc[p4[q] + 1] = dv[q].y;
+                            if (m & 4u) Dacc[p4[q] + 2] = dv[q].z;
+                            if (m & 8u) Dacc[p4[q] + 3] = dv[q].w;
+                        }
                     }
                 }
             }
-            events += phi - plo;
             __syncthreads();
         }
     }
@@ -623,6 +629,7 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
         }
     }
     __syncthreads();
+    const unsigned long long events = block_sum64(ev_local, red64);
     const unsigned long long exc_total = block_sum64(exc_events, red64);
     if (tid == 0 && events) {
         atomicAdd(&stats[c & 63].events, events);
