@@ -118,7 +118,7 @@ std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
         sizeof(float) * Se,                               // P
         sizeof(float) * N, sizeof(float) * N,             // v, u
         (c->sum_mode == DPSNN_SUM_FIXED ? 8 : 4) * N,     // acc
-        sizeof(uint32_t) * N, sizeof(int32_t) * N, sizeof(int32_t) * N,  // hist, t_old, t_last
+        sizeof(uint2) * N, sizeof(int32_t) * N,           // hist (with t_old), t_last
         sizeof(uint64_t) * (size_t)d.R * d.C * d.W,       // ring
         sizeof(DevStats) * 64,                            // stats
         sizeof(uint32_t) * (N / 1024 + 2),                // scan_tmp
@@ -440,7 +440,7 @@ NetDesc Net::make_desc() const {
     nd.t0 = t;
     nd.colmap = colmap; nd.srcmap = srcmap; nd.seg_off = seg_off; nd.tgt = tgt;
     nd.w = w; nd.Dacc = Dacc; nd.rowptr = rowptr; nd.rev_srcd = rev_srcd; nd.rev_fwd = rev_fwd;
-    nd.Pacc = Pacc; nd.v = v; nd.u = u; nd.acc = acc; nd.hist = hist; nd.t_old = t_old;
+    nd.Pacc = Pacc; nd.v = v; nd.u = u; nd.acc = acc; nd.hist = hist;
     nd.t_last = t_last; nd.ring = ring; nd.tp = tp; nd.tm = tm; nd.tp_len = tp_len;
     nd.tm_len = tm_len; nd.stats = stats; nd.thal_whole = thal_whole; nd.thal_thr = thal_thr;
     nd.thal_mv = cfg.thalamic_current; nd.stim_t = stim_t; nd.stim_id = stim_id;
@@ -566,7 +566,7 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     n->rowptr = (uint32_t*)p[k++]; n->cursor = (uint32_t*)p[k++];
     n->rev_srcd = (uint32_t*)p[k++]; n->rev_fwd = (uint32_t*)p[k++]; n->Pacc = (float*)p[k++];
     n->v = (float*)p[k++]; n->u = (float*)p[k++]; n->acc = p[k++];
-    n->hist = (uint32_t*)p[k++]; n->t_old = (int32_t*)p[k++]; n->t_last = (int32_t*)p[k++];
+    n->hist = (uint2*)p[k++]; n->t_last = (int32_t*)p[k++];
     n->ring = (uint64_t*)p[k++]; n->stats = (DevStats*)p[k++]; n->scan_tmp = (uint32_t*)p[k++];
     if (cfg->sum_mode == DPSNN_SUM_ORDERED) {
         n->ev_cnt = (uint32_t*)p[k++]; n->ev_start = (uint32_t*)p[k++];

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_fill_rows(Dims d, const uint32_t* __res
 }
 
 __global__ void k_init_state(Dims d, float* __restrict__ v, float* __restrict__ u,
-                             uint32_t* __restrict__ hist, int32_t* __restrict__ t_old,
+                             uint2* __restrict__ hist,
                              int32_t* __restrict__ t_last) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.N) return;
@@ -123,8 +123,7 @@ __global__ void k_init_state(Dims d, float* __restrict__ v, float* __restrict__ 
     (void)l;
     v[k] = c;
     u[k] = b * c;
-    hist[k] = 0u;
-    t_old[k] = kNoSpike;
+    hist[k] = make_uint2(0u, (uint32_t)kNoSpike);
     t_last[k] = kNoSpike;
 }
 
@@ -204,7 +203,7 @@ hipError_t launch_build(Net& n) {
                            n.rev_fwd);
     }
     hipLaunchKernelGGL(k_init_state, dim3((d.N + 255) / 256), dim3(256), 0, n.stream, d, n.v, n.u,
-                       n.hist, n.t_old, n.t_last);
+                       n.hist, n.t_last);
     return hipGetLastError();
 }
 

@@ -58,8 +58,7 @@ struct NetDesc {
     float* v;
     float* u;
     void* acc;                       // long long or float [N]
-    uint32_t* hist;
-    int32_t* t_old;
+    uint2* hist;                     // [N] x: spike history bits, y: t_old (int32)
     int32_t* t_last;
     uint64_t* ring;
     const float* tp;

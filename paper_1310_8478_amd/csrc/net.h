@@ -113,8 +113,9 @@ struct Net {
     float* v = nullptr;
     float* u = nullptr;
     void* acc = nullptr;          // long long[N] (FIXED) or float[N]
-    uint32_t* hist = nullptr;     // [N] bit b: spiked at (latest stamp time) - b
-    int32_t* t_old = nullptr;     // [N] latest stamp older than the history window
+    // [N] x: bit b set if spiked at (latest stamp time) - b; y: latest stamp
+    // older than that 32-step window (int32), so one 8-byte load gives both
+    uint2* hist = nullptr;
     int32_t* t_last = nullptr;    // [N] latest stamp
     uint64_t* ring = nullptr;     // [R*C*W]
     float* tp = nullptr;          // [tp_len] LTP amplitudes by dt

@@ -40,8 +40,7 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
     const uint32_t t = nd.t0 + tstep;
     if (t < 1) return;  // no stamp 0: nothing to potentiate in the first step
     const uint64_t* __restrict__ ring = nd.ring;
-    const uint32_t* __restrict__ hist = nd.hist;
-    const int32_t* __restrict__ t_old = nd.t_old;
+    const uint2* __restrict__ hist = nd.hist;
     const uint32_t* __restrict__ rowptr = nd.rowptr;
     const uint32_t* __restrict__ rev_srcd = nd.rev_srcd;
     float* __restrict__ P = nd.Pacc;
@@ -83,7 +82,7 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
         for (uint32_t x = tid; x < nwin; x += BS) {
             const uint32_t q = x / d.Ncol;
             const uint32_t l = x - q * d.Ncol;
-            hwin[x] = hist[smap[q] * d.Ncol + l];
+            hwin[x] = hist[smap[q] * d.Ncol + l].x;
         }
     }
     unsigned long long visits = 0;
@@ -101,13 +100,13 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
             const uint32_t l = (sd >> 6) & 0xFFFFu;
             const uint32_t sl = sd >> 22;
             const uint32_t p = smap[sl] * d.Ncol + l;
-            const uint32_t h = stage ? hwin[sl * d.Ncol + l] : hist[p];
-            const uint32_t m = h >> dl;
+            const uint2 ht = stage ? make_uint2(hwin[sl * d.Ncol + l], 0u) : hist[p];
+            const uint32_t m = ht.x >> dl;
             uint32_t dt;
             if (m) {
                 dt = (uint32_t)__ffs((int)m) - 1u;
             } else {
-                const int32_t to = t_old[p];
+                const int32_t to = (int32_t)(stage ? hist[p].y : ht.y);
                 if (to == kNoSpike) return pv;
                 dt = (uint32_t)((int64_t)t - dl - to);
             }
@@ -232,13 +231,13 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
                 const uint32_t l = (sd[q] >> 6) & 0xFFFFu;
                 const uint32_t s = sd[q] >> 22;
                 const uint32_t p = smap[s] * d.Ncol + l;
-                const uint32_t h = stage ? hwin[s * d.Ncol + l] : hist[p];
-                const uint32_t m = h >> dl;
+                const uint2 ht = stage ? make_uint2(hwin[s * d.Ncol + l], 0u) : hist[p];
+                const uint32_t m = ht.x >> dl;
                 uint32_t dt;
                 if (m) {
                     dt = (uint32_t)__ffs((int)m) - 1u;
                 } else {
-                    const int32_t to = t_old[p];
+                    const int32_t to = (int32_t)(stage ? hist[p].y : ht.y);
                     if (to == kNoSpike) continue;
                     dt = (uint32_t)((int64_t)t - dl - to);
                 }
@@ -737,8 +736,7 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
     float* __restrict__ v = nd.v;
     float* __restrict__ u = nd.u;
     void* __restrict__ acc_v = nd.acc;
-    uint32_t* __restrict__ hist = nd.hist;
-    int32_t* __restrict__ t_old = nd.t_old;
+    uint32_t* __restrict__ hist32 = (uint32_t*)nd.hist;  // x, y interleaved
     int32_t* __restrict__ t_last = nd.t_last;
     uint64_t* __restrict__ ring = nd.ring;
     const uint32_t thal_whole = nd.thal_whole, thal_thr = nd.thal_thr;
@@ -858,9 +856,9 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
         v[k] = vv;
         u[k] = uu;
         // history: bit b <-> stamp (t + 1) - b after the shift
-        const uint32_t h = hist[k];
-        if (h >> 31) t_old[k] = (int32_t)t - 31;
-        hist[k] = (h << 1) | (fired ? 1u : 0u);
+        const uint32_t h = hist32[2 * (size_t)k];
+        if (h >> 31) hist32[2 * (size_t)k + 1] = (uint32_t)((int32_t)t - 31);
+        hist32[2 * (size_t)k] = (h << 1) | (fired ? 1u : 0u);
         if (fired) t_last[k] = (int32_t)t + 1;
         if (MODE == DPSNN_SUM_FIXED) ((long long*)acc_v)[k] = 0;
         else ((float*)acc_v)[k] = 0.0f;
