@@ -293,6 +293,15 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
         if (nch > 0xFFFFFFFFull) return fail(DPSNN_E_INVAL, "too many consolidation chunks");
         for (uint64_t q = 0; q < nch; ++q) wu[k].push_back(make_uint2(0u, (uint32_t)q));
     }
+    // heaviest columns first (synapses per column), so that the longest
+    // workgroups start early; stable, so a single network keeps its order
+    if (cnt > 1) {
+        std::stable_sort(col.begin(), col.end(), [&](const uint2& a, const uint2& b) {
+            const uint64_t wa = (uint64_t)m[a.x]->d.Ncol * m[a.x]->d.M;
+            const uint64_t wb = (uint64_t)m[b.x]->d.Ncol * m[b.x]->d.M;
+            return wa > wb;
+        });
+    }
     L.n_col = (uint32_t)col.size();
     L.n_neu = (uint32_t)neu.size();
     {
