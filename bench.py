@@ -519,15 +519,23 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s1 = net.stats()
-    # the per-kernel timers add a few events per step; the same steps again
-    # without them give the step time a caller sees (matters at small sizes)
-    net.set_timing(False)
-    n_plain = min(args.steps, 500)
-    t0 = time.perf_counter()
-    net.step(n_plain)
-    net.sync()
-    ms_plain = 1000.0 * (time.perf_counter() - t0) / n_plain
     net.close()
+    # the per-kernel timers add a few events per step, which matters for
+    # short steps: the same steps again on a fresh network, without timers,
+    # give the step time a caller sees
+    ms_plain = None
+    if 1000.0 * wall / args.steps < 2.0:
+        net = dp.Network(cfg, device=0)
+        for kv in filter(None, args.tune.split(",")):
+            k, v = kv.split("=")
+            net.set_tuning(int(k), int(v))
+        net.step(args.warmup)
+        net.sync()
+        t0 = time.perf_counter()
+        net.step(args.steps)
+        net.sync()
+        ms_plain = 1000.0 * (time.perf_counter() - t0) / args.steps
+        net.close()
 
     d = {k: s1[k] - s0[k] for k in s1 if isinstance(s1[k], (int, float))}
     N = cfg["grid_x"] * cfg["grid_y"] * cfg["neurons_per_column"]

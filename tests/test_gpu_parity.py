@@ -220,6 +220,22 @@ def test_dense_regime_column_parts(dp):
         assert g["stats"]["ltp_visits"] == ref["stats"]["ltp_visits"]
 
 
+def test_sparse_regime_shapes_invariance(dp):
+    # 2048 columns at ~20 Hz: the automatic shapes switch to the sparse ones
+    # (own-column window, 256-thread workgroups, no LTP staging) once the
+    # measured event rate arrives; results equal those of the dense shapes
+    cfg = W.paper_shaped(grid=(64, 32), M=50, thalamic_rate=24.0, weight_update_period=100)
+    T = 160
+    _say("sparse regime: automatic shapes vs forced dense shapes, 64x32 grid")
+    dense = ((0, 1024), (1, 1024), (2, 1), (4, 1), (6, 1))
+    g = gpu_run(dp, cfg, T, conn=False)
+    ref = gpu_run(dp, cfg, T, tuning=dense, conn=False)
+    assert len(ref["tt"]) > 64 * 32 * 1000 * 5 * T / 1000, "the network must be active"
+    assert_bitexact(g, ref, conn=False)
+    assert g["stats"]["events"] == ref["stats"]["events"]
+    assert g["stats"]["ltp_visits"] == ref["stats"]["ltp_visits"]
+
+
 @pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
 def test_launch_shape_invariance(dp, orc, mode):
     # the paper checks identical spikes for every process count (Sec. 3); here
