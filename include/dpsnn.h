@@ -171,14 +171,24 @@ int dpsnn_set_stimulus(dpsnn_net *net, const uint32_t *t, const uint32_t *id,
  * accumulated into dpsnn_stats at the next dpsnn_get_stats. */
 int dpsnn_set_timing(dpsnn_net *net, int enable);
 
-/* Launch-shape knobs (results never depend on them): key 0 = delivery block
- * size, 1 = LTP block size, 2 = LDS current window in delivery (1 = over all
- * 13 reachable columns, 2 = over the own column only, 0 = off),
- * 3 = events-per-lane unroll in delivery (1, 2, 4 or 8), 4 = LDS copy of the
- * targets' spike ages in delivery (1 on, 0 off), 5 = workgroups per column in
- * delivery and LTP (0 = automatic: networks with few columns split each
- * column's work; 1 .. 1024 = that many; summation mode ORDERED always 1),
- * 6 = LDS copy of the sources' spike history in LTP (1 allowed, 0 off). */
+/* Launch-shape knobs (results never depend on them).  "Automatic" values
+ * (the defaults) follow the measured regime of the launch: a launch over at
+ * least 2048 columns whose source columns deliver fewer events per step than
+ * their current window has entries is sparse, every other launch dense.
+ *   key 0: delivery workgroup size 256, 512, 1024; 0 = automatic (256 / 1024)
+ *   key 1: LTP workgroup size 256, 512, 1024; 0 = automatic (256 / 1024)
+ *   key 2: LDS current window in delivery: 1 = over all 13 reachable
+ *          columns, 2 = over the own column only, 0 = off; 3 = automatic
+ *          (2 / 1); a window that does not fit in LDS falls back to 2, then 0
+ *   key 3: quads in flight per lane in delivery x 2 (1, 2, 4 or 8; default 4)
+ *   key 4: LDS copy of the targets' spike ages in delivery: 1 on, 0 off,
+ *          2 = automatic (off / on)
+ *   key 5: workgroups per column in delivery and LTP: 0 = automatic (sets of
+ *          fewer than 512 columns split each column's work), 1 .. 1024 = that
+ *          many; summation mode ORDERED always 1
+ *   key 6: LDS copy of the sources' spike history in LTP: 1 allowed, 0 off,
+ *          2 = automatic (off / allowed)
+ * (sparse / dense choice in parentheses) */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 
 /* Online autotuner of the launch shapes (the knobs of dpsnn_set_tuning):
