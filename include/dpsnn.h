@@ -180,7 +180,8 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *   key 2: LDS current window in delivery: 1 = over all 13 reachable
  *          columns, 2 = over the own column only, 0 = off; 3 = automatic
  *          (2 / 1); a window that does not fit in LDS falls back to 2, then 0
- *   key 3: quads in flight per lane in delivery x 2 (1, 2, 4 or 8; default 4)
+ *   key 3: delivery unroll U = 1, 2, 4 or 8 (default 4): each lane keeps
+ *          max(1, U / 2) quads of 4 consecutive synapses in flight
  *   key 4: LDS copy of the targets' spike ages in delivery: 1 on, 0 off,
  *          2 = automatic (off / on)
  *   key 5: workgroups per column in delivery and LTP: 0 = automatic (sets of
