@@ -75,7 +75,10 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
     const uint32_t be_ = block_scan(ce, sh, nends);
     if (tid < kSlots) smap[tid] = srcmap[ct * kSlots + tid];
     if (tid < 64) tph[tid] = tid < tp_len ? tp[tid] : 0.0f;
-    const bool stage = allow_stage && nparts == 1u && (nsp * 8u >= d.Ncol);
+    // stage the 13 source columns' history when the expected visits (spiking
+    // targets x about 0.8 M incoming excitatory synapses each) outnumber it
+    const bool stage = allow_stage && nparts == 1u &&
+                       (uint64_t)nsp * d.M * 4u >= 5ull * kSlots * d.Ncol;
     __syncthreads();
     if (stage) {
         const uint32_t nwin = kSlots * d.Ncol;
