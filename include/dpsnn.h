@@ -100,7 +100,9 @@ typedef struct dpsnn_stats {
     uint64_t ltp_visits;      /* incoming excitatory synapses walked by LTP */
     uint64_t consolidations;  /* weight-update passes run */
     uint64_t events_exc;      /* deliveries through excitatory (plastic) synapses */
-    /* per-kernel device time, accumulated only while timing is enabled */
+    /* per-kernel device time, accumulated only while timing is enabled;
+     * launches of at most 256 column workgroups run LTP and delivery as one
+     * kernel, counted under delivery */
     double   ms_ltp, ms_deliver, ms_neuron, ms_wupdate;
     uint64_t n_ltp, n_deliver, n_neuron, n_wupdate;
 } dpsnn_stats;

@@ -29,12 +29,12 @@ namespace {
 // latest stamp older than the 32-step window.
 // ---------------------------------------------------------------------------
 template <int U>
-__global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
-                                              const uint2* __restrict__ bmap, uint32_t allow_stage,
-                                              uint32_t nparts, uint32_t tstep) {
-    // block: part `part` of the column of map entry blockIdx.x / nparts
-    const uint2 br = bmap[blockIdx.x / nparts];
-    const uint32_t part = blockIdx.x % nparts;
+__device__ __forceinline__ void ltp_body(const NetDesc* __restrict__ nds,
+                                         const uint2* __restrict__ bmap, uint32_t allow_stage,
+                                         uint32_t nparts, uint32_t tstep, uint32_t bid) {
+    // workgroup bid: part `part` of the column of map entry bid / nparts
+    const uint2 br = bmap[bid / nparts];
+    const uint32_t part = bid % nparts;
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
     const uint32_t t = nd.t0 + tstep;
@@ -254,6 +254,13 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
     if (tid == 0 && visits) atomicAdd(&stats[ct & 63].ltp_visits, visits);
 }
 
+template <int U>
+__global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
+                                              const uint2* __restrict__ bmap, uint32_t allow_stage,
+                                              uint32_t nparts, uint32_t tstep) {
+    ltp_body<U>(nds, bmap, allow_stage, nparts, tstep, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Delivery, current injection and LTD (items 2.3-2.6).  A spike stamped s
 // reaches the synapses of delay d in step s + d - 1 (its current first moves
@@ -267,14 +274,14 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
 // columns, 2 window over the own column only (targets in the neighbour
 // columns take global atomics; small LDS, several workgroups per CU).
 template <bool FIXED, int WIN, typename TgtT, int U>
-__global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nds,
-                                                  const uint2* __restrict__ bmap,
-                                                  uint32_t allow_age, uint32_t nparts,
-                                                  unsigned long long* __restrict__ set_events,
-                                                  uint32_t tstep) {
-    // block: part `part` of the column of map entry blockIdx.x / nparts
-    const uint2 br = bmap[blockIdx.x / nparts];
-    const uint32_t part = blockIdx.x % nparts;
+__device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
+                                             const uint2* __restrict__ bmap,
+                                             uint32_t allow_age, uint32_t nparts,
+                                             unsigned long long* __restrict__ set_events,
+                                             uint32_t tstep, uint32_t bid) {
+    // workgroup bid: part `part` of the column of map entry bid / nparts
+    const uint2 br = bmap[bid / nparts];
+    const uint32_t part = bid % nparts;
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
     const uint32_t t = nd.t0 + tstep;
@@ -640,6 +647,33 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
     }
 }
 
+template <bool FIXED, int WIN, typename TgtT, int U>
+__global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nds,
+                                                  const uint2* __restrict__ bmap,
+                                                  uint32_t allow_age, uint32_t nparts,
+                                                  unsigned long long* __restrict__ set_events,
+                                                  uint32_t tstep) {
+    deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, set_events, tstep, blockIdx.x);
+}
+
+// LTP and delivery of one step in a single launch, for launches small enough
+// that kernel boundaries dominate: the first n_ltp workgroups run LTP, the
+// rest delivery.  The two write disjoint state (P; currents and D) and read
+// nothing the other writes, so they may run concurrently.
+template <bool FIXED, int WIN, typename TgtT, int U>
+__global__ __launch_bounds__(1024) void k_ltp_deliver(const NetDesc* __restrict__ nds,
+                                                      const uint2* __restrict__ bmap,
+                                                      uint32_t allow_stage, uint32_t allow_age,
+                                                      uint32_t nparts,
+                                                      unsigned long long* __restrict__ set_events,
+                                                      uint32_t tstep, uint32_t n_ltp) {
+    if (blockIdx.x < n_ltp)
+        ltp_body<4>(nds, bmap, allow_stage, nparts, tstep, blockIdx.x);
+    else
+        deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, set_events, tstep,
+                                          blockIdx.x - n_ltp);
+}
+
 // ---------------------------------------------------------------------------
 // ORDERED mode: the same deliveries, recorded per target with their canonical
 // key (delay, source id, rank within the source's delay-d synapses, which is
@@ -957,9 +991,16 @@ uint32_t column_parts(const LaunchSet& L, const Tuning& tune) {
     return (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, cap), 1024u);
 }
 
+// LTP launch parameters handed to launch_deliver when the two are fused.
+struct FusedLtp {
+    bool on = false;
+    uint32_t allow_stage = 0;
+    size_t lds = 0;
+};
+
 template <typename TgtT>
 hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, Net* const* members,
-                          uint32_t nparts, uint32_t tstep) {
+                          uint32_t nparts, uint32_t tstep, const FusedLtp& fl) {
     if (L.sum_mode == DPSNN_SUM_ORDERED) {
         // one network only (checked when the set is made)
         Net& n = *members[0];
@@ -989,11 +1030,21 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
     const size_t lds0 = (wmode == 1 ? win_full : (wmode == 2 ? win_own : 0)) + base;
     const uint32_t allow_age = (tune.age && lds0 + agew + 256 <= tune.max_lds) ? 1u : 0u;
     const size_t lds = lds0 + (allow_age ? agew : 0);
+    const uint32_t nblk = L.n_col * nparts;
 #define DPSNN_DELIVER(FX, WN, UU)                                                              \
     do {                                                                                       \
-        allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                           \
-        hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(L.n_col * nparts), dim3(BS), lds, \
-                           stream, L.descs, L.bmap_col, allow_age, nparts, L.ev_count, tstep); \
+        if (fl.on) {                                                                           \
+            const size_t lf = std::max(lds, fl.lds);                                           \
+            allow_lds(k_ltp_deliver<FX, WN, TgtT, UU>, lf);                                    \
+            hipLaunchKernelGGL((k_ltp_deliver<FX, WN, TgtT, UU>), dim3(2 * nblk), dim3(BS), lf, \
+                               stream, L.descs, L.bmap_col, fl.allow_stage, allow_age, nparts, \
+                               L.ev_count, tstep, nblk);                                      \
+        } else {                                                                               \
+            allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                       \
+            hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(nblk), dim3(BS), lds,       \
+                               stream, L.descs, L.bmap_col, allow_age, nparts, L.ev_count,     \
+                               tstep);                                                         \
+        }                                                                                      \
     } while (0)
 #define DPSNN_DELIVER_W(FX, UU)                                                                \
     do {                                                                                       \
@@ -1131,16 +1182,24 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipS
         const size_t hw = (size_t)kSlots * L.max_ncol * sizeof(uint32_t);
         const uint32_t allow = (tune.ltp_stage && base + hw <= tune.max_lds) ? 1u : 0u;
         const size_t lds = base + (allow ? hw : 0);
-        allow_lds(k_ltp<4>, lds);
         const uint32_t nparts = column_parts(L, tune);
-        tm.begin(0, stream);
-        hipLaunchKernelGGL(k_ltp<4>, dim3(L.n_col * nparts), dim3(BS), lds, stream, L.descs,
-                           L.bmap_col, allow, nparts, tstep);
-        tm.end(stream);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // small launches run LTP and delivery as one kernel (same workgroup size)
+        FusedLtp fl;
+        const uint32_t BSd = std::max<uint32_t>(tune.deliver_block, ((L.max_w + 63) / 64) * 64);
+        fl.on = L.sum_mode != DPSNN_SUM_ORDERED && BSd == BS && (uint64_t)L.n_col * nparts <= 256u;
+        fl.allow_stage = allow;
+        fl.lds = lds;
+        if (!fl.on) {
+            allow_lds(k_ltp<4>, lds);
+            tm.begin(0, stream);
+            hipLaunchKernelGGL(k_ltp<4>, dim3(L.n_col * nparts), dim3(BS), lds, stream, L.descs,
+                               L.bmap_col, allow, nparts, tstep);
+            tm.end(stream);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         tm.begin(1, stream);
-        e = L.tgt16 ? launch_deliver<uint16_t>(L, tune, stream, members, nparts, tstep)
-                    : launch_deliver<uint32_t>(L, tune, stream, members, nparts, tstep);
+        e = L.tgt16 ? launch_deliver<uint16_t>(L, tune, stream, members, nparts, tstep, fl)
+                    : launch_deliver<uint32_t>(L, tune, stream, members, nparts, tstep, fl);
         tm.end(stream);
         if (e != hipSuccess) return e;
         L.steps++;
