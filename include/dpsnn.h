@@ -101,8 +101,8 @@ typedef struct dpsnn_stats {
     uint64_t consolidations;  /* weight-update passes run */
     uint64_t events_exc;      /* deliveries through excitatory (plastic) synapses */
     /* per-kernel device time, accumulated only while timing is enabled;
-     * launches of at most 256 column workgroups run LTP and delivery as one
-     * kernel, counted under delivery */
+     * when LTP and delivery run as one kernel (dpsnn_set_tuning key 7) their
+     * time is counted under delivery */
     double   ms_ltp, ms_deliver, ms_neuron, ms_wupdate;
     uint64_t n_ltp, n_deliver, n_neuron, n_wupdate;
 } dpsnn_stats;
@@ -191,12 +191,17 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *          many; summation mode ORDERED always 1
  *   key 6: LDS copy of the sources' spike history in LTP: 1 allowed, 0 off,
  *          2 = automatic (off / allowed)
+ *   key 7: LTP and delivery run as one kernel when each launch has at most
+ *          this many workgroups and both use the same workgroup size
+ *          (default 2^32 - 1, i.e. always; 0 = never)
  * (sparse / dense choice in parentheses) */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 
 /* Online autotuner of the launch shapes (the knobs of dpsnn_set_tuning):
  * steps the network steps_per_trial steps under each candidate shape, in two
- * interleaved rounds, and keeps the fastest delivery and LTP shapes.  The
+ * interleaved rounds, and keeps the fastest: with LTP and delivery fused (key
+ * 7, the default) one workgroup size for both plus the delivery unroll, by
+ * their combined time; otherwise the delivery and LTP shapes separately.  The
  * network advances by those steps; its results do not depend on the shapes. */
 int dpsnn_autotune(dpsnn_net *net, uint32_t steps_per_trial);
 

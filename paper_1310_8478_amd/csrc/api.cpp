@@ -390,19 +390,26 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
             if (value > 2) return fail(DPSNN_E_INVAL, "LTP staging must be 0 (off), 1 (on) or 2 (automatic)");
             tn.ltp_stage = value;
             return DPSNN_OK;
+        case 7:
+            tn.fuse = value;
+            return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");
     }
 }
 
 // Online autotuner: each candidate shape runs `steps` steps (two interleaved
-// rounds); the fastest delivery shape and the fastest LTP block are kept.
+// rounds).  With LTP and delivery fused (the default) a candidate is one
+// workgroup size for both plus the delivery unroll, judged by their combined
+// time; with fusion off the fastest delivery shape and the fastest LTP
+// workgroup size are kept separately.
 int autotune(LaunchSet& L, Tuning& tn, Timers& tm, hipStream_t stream, Net* const* m, uint32_t steps) {
     if (steps == 0) return fail(DPSNN_E_INVAL, "steps_per_trial must be positive");
     struct Cand { uint32_t block, unroll; };
     const Cand dcand[] = {{256, 4}, {512, 4}, {1024, 4}, {256, 8}, {512, 8}, {1024, 8}};
     const uint32_t lcand[] = {256, 512, 1024};
     const size_t nd = sizeof(dcand) / sizeof(dcand[0]);
+    const bool joint = tn.fuse != 0;
     std::vector<double> dms(nd, 0.0), lms(3, 0.0);
     std::vector<uint64_t> dn(nd, 0), ln(3, 0);
     Timers probe;
@@ -413,7 +420,7 @@ int autotune(LaunchSet& L, Tuning& tn, Timers& tm, hipStream_t stream, Net* cons
             Tuning trial = base;
             trial.deliver_block = dcand[c].block;
             trial.unroll = dcand[c].unroll;
-            trial.ltp_block = lcand[c % 3];
+            trial.ltp_block = joint ? dcand[c].block : lcand[c % 3];
             for (uint32_t s = 0; s < steps; ++s) {
                 hipError_t e = launch_step_set(L, trial, probe, stream, m);
                 if (e != hipSuccess) { probe.release(); return fail(DPSNN_E_DEVICE, hipGetErrorString(e)); }
@@ -422,20 +429,29 @@ int autotune(LaunchSet& L, Tuning& tn, Timers& tm, hipStream_t stream, Net* cons
             double before[4] = {probe.ms[0], probe.ms[1], probe.ms[2], probe.ms[3]};
             uint64_t nbefore[4] = {probe.n[0], probe.n[1], probe.n[2], probe.n[3]};
             probe.collect();
-            dms[c] += probe.ms[1] - before[1];
-            dn[c] += probe.n[1] - nbefore[1];
-            lms[c % 3] += probe.ms[0] - before[0];
-            ln[c % 3] += probe.n[0] - nbefore[0];
+            if (joint) {  // one step = LTP (if launched apart) + delivery
+                dms[c] += (probe.ms[0] - before[0]) + (probe.ms[1] - before[1]);
+                dn[c] += probe.n[1] - nbefore[1];
+            } else {
+                dms[c] += probe.ms[1] - before[1];
+                dn[c] += probe.n[1] - nbefore[1];
+                lms[c % 3] += probe.ms[0] - before[0];
+                ln[c % 3] += probe.n[0] - nbefore[0];
+            }
         }
     }
     probe.release();
     size_t bd = 0, bl = 0;
     for (size_t c = 1; c < nd; ++c)
         if (dn[c] && (!dn[bd] || dms[c] / dn[c] < dms[bd] / dn[bd])) bd = c;
-    for (size_t c = 1; c < 3; ++c)
-        if (ln[c] && (!ln[bl] || lms[c] / ln[c] < lms[bl] / ln[bl])) bl = c;
     if (dn[bd]) { tn.deliver_block = dcand[bd].block; tn.unroll = dcand[bd].unroll; }
-    if (ln[bl]) tn.ltp_block = lcand[bl];
+    if (joint) {
+        if (dn[bd]) tn.ltp_block = dcand[bd].block;
+    } else {
+        for (size_t c = 1; c < 3; ++c)
+            if (ln[c] && (!ln[bl] || lms[c] / ln[c] < lms[bl] / ln[bl])) bl = c;
+        if (ln[bl]) tn.ltp_block = lcand[bl];
+    }
     (void)tm;
     return DPSNN_OK;
 }

@@ -25,6 +25,7 @@ struct Tuning {
     uint32_t age = 2;             // LDS target spike ages: 0 off, 1 on, 2 auto (off / on)
     uint32_t parts = 0;           // workgroups per column (0: chosen per launch set)
     uint32_t ltp_stage = 2;       // LDS source spike history in LTP: 0, 1, 2 auto (0 / 1)
+    uint32_t fuse = 0xFFFFFFFFu;  // LTP + delivery as one kernel up to this many workgroups each
     size_t max_lds = 65536;
 };
 

@@ -1186,7 +1186,8 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipS
         // small launches run LTP and delivery as one kernel (same workgroup size)
         FusedLtp fl;
         const uint32_t BSd = std::max<uint32_t>(tune.deliver_block, ((L.max_w + 63) / 64) * 64);
-        fl.on = L.sum_mode != DPSNN_SUM_ORDERED && BSd == BS && (uint64_t)L.n_col * nparts <= 256u;
+        fl.on = L.sum_mode != DPSNN_SUM_ORDERED && BSd == BS &&
+                (uint64_t)L.n_col * nparts <= tune.fuse;
         fl.allow_stage = allow;
         fl.lds = lds;
         if (!fl.on) {
