@@ -202,6 +202,7 @@ TUNINGS = [
     ((0, 256),), ((0, 512), (3, 1)), ((2, 0),), ((3, 2), (1, 1024)), ((2, 0), (0, 256), (3, 1)),
     ((5, 1),), ((5, 3),), ((5, 7), (2, 0)), ((5, 64), (0, 256), (1, 512)),
     ((2, 2),), ((2, 2), (6, 0), (0, 512), (1, 256)), ((2, 2), (5, 5), (3, 4)), ((6, 0),),
+    ((7, 0),), ((7, 0), (5, 3), (3, 8)),
 ]
 
 
