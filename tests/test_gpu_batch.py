@@ -121,3 +121,40 @@ def test_batch_rules(dp):
     finally:
         a.close()
         o.close()
+
+
+def _events_from_raster(tt, ii, dly, M, T, dmax):
+    """Deliveries implied by a raster: a spike stamped s reaches its delay-d
+    synapses in step s + d - 1, which lies in steps 0 .. T-1 when d <= T - s."""
+    d = dly.reshape(-1, M).astype(np.int64)
+    cum = np.zeros((d.shape[0], dmax + 1), dtype=np.int64)
+    for k in range(1, dmax + 1):
+        cum[:, k] = (d <= k).sum(axis=1)
+    lim = np.minimum(T - tt.astype(np.int64), dmax)
+    ok = lim >= 1
+    return int(cum[ii[ok].astype(np.int64), lim[ok]].sum())
+
+
+def test_batch_atomic_mode(dp):
+    # unordered fp32 atomics: not bit-reproducible, so the batch is checked
+    # for exact delivery accounting against its own raster and for a mean
+    # rate close to the fixed-point run of the same networks
+    T = 300
+    _say("batch of 5 networks, ATOMIC summation")
+    nets = [dp.Network(dict(c, sum_mode=W.SUM_ATOMIC)) for c in MIX]
+    b = dp.Batch(nets)
+    b.step(T)
+    b.close()
+    for cfg, n in zip(MIX, nets):
+        tt, ii = n.read_spikes(1, T + 1)
+        _, dly = n.read_connectivity()
+        st = n.stats()
+        assert st["events"] == _events_from_raster(tt, ii, dly, cfg["synapses_per_neuron"], T,
+                                                   cfg["max_delay"])
+        ref = dp.Network(cfg)
+        ref.step(T)
+        ref.sync()
+        rt, _ = ref.read_spikes(1, T + 1)
+        ref.close()
+        assert abs(len(tt) - len(rt)) <= 0.25 * len(rt) + 100, (len(tt), len(rt))
+        n.close()

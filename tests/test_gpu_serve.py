@@ -239,3 +239,34 @@ def test_shutdown_with_jobs_in_flight(dp):
     # the device is still usable afterwards
     got = solo(dp, W.tiny(), 30)
     assert len(got["tt"]) > 0
+
+
+def test_mixed_summation_modes(dp):
+    # fixed-point, ordered and atomic jobs in one server: three groups step
+    # side by side; the reproducible ones equal their solo runs, the atomic
+    # one delivers exactly the events its raster implies
+    _say("serve: fixed, ordered and atomic jobs together")
+    jobs = [JOBS[0], JOBS[3],
+            (dict(JOBS[2][0], sum_mode=W.SUM_ATOMIC), 180),
+            (dict(JOBS[9][0], sum_mode=W.SUM_ATOMIC), 120)]
+    srv = dp.Server(max_quantum=6)
+    try:
+        ids, got = run_stream(dp, srv, jobs, first_batch=4)
+        dlys = {}
+        for j, (cfg, steps) in zip(ids, jobs):
+            if cfg["sum_mode"] == W.SUM_ATOMIC:
+                dlys[j] = srv.job_network(j).read_connectivity()[1]
+            srv.release(j)
+    finally:
+        srv.close()
+    for (cfg, steps), j in zip(jobs, ids):
+        g = got[j]
+        if cfg["sum_mode"] != W.SUM_ATOMIC:
+            assert_same(g, solo(dp, cfg, steps), f"job {j}")
+            continue
+        M = cfg["synapses_per_neuron"]
+        d = dlys[j].reshape(-1, M).astype(np.int64)
+        cum = np.stack([(d <= k).sum(axis=1) for k in range(cfg["max_delay"] + 1)], axis=1)
+        lim = np.minimum(steps - g["tt"].astype(np.int64), cfg["max_delay"])
+        ok = lim >= 1
+        assert g["stats"]["events"] == int(cum[g["ii"][ok].astype(np.int64), lim[ok]].sum())
