@@ -105,6 +105,7 @@ typedef struct dpsnn_stats {
      * time is counted under delivery */
     double   ms_ltp, ms_deliver, ms_neuron, ms_wupdate;
     uint64_t n_ltp, n_deliver, n_neuron, n_wupdate;
+    uint64_t graph_steps;     /* steps run as replays of a captured graph */
 } dpsnn_stats;
 
 typedef struct dpsnn_net dpsnn_net;
@@ -129,7 +130,12 @@ int dpsnn_build_network(const dpsnn_config *cfg, const dpsnn_device *dev, dpsnn_
 /* Enqueue n_steps 1 ms steps (Sec. 2, loop items 2.1-2.7, plus the periodic
  * consolidation).  Asynchronous on the network's stream, except that the
  * call waits when it gets more than about 16 steps ahead of the device (the
- * automatic launch shapes follow a measured event rate at most that stale). */
+ * automatic launch shapes follow a measured event rate at most that stale).
+ * Runs of G steps (dpsnn_set_tuning key 8, default 8) that hold no
+ * consolidation and not the first step are enqueued as one replay of a HIP
+ * graph captured for that run length and the current launch shapes (captured
+ * again when either changes); with timing enabled every step is launched
+ * directly.  The results are the same either way. */
 int dpsnn_step(dpsnn_net *net, uint32_t n_steps);
 
 /* Wait for all enqueued work of the network. */
@@ -194,6 +200,8 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *   key 7: LTP and delivery run as one kernel when each launch has at most
  *          this many workgroups and both use the same workgroup size
  *          (default 2^32 - 1, i.e. always; 0 = never)
+ *   key 8: steps per captured graph G, 0 .. 1024 (default 8; 0 = every step
+ *          launched directly)
  * (sparse / dense choice in parentheses) */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 
@@ -219,6 +227,8 @@ void dpsnn_destroy(dpsnn_net *net);
 typedef struct dpsnn_batch dpsnn_batch;
 
 int dpsnn_batch_create(dpsnn_net *const *nets, uint32_t n_nets, dpsnn_batch **out);
+/* n_steps steps of every member, graphed like dpsnn_step (one graph holds the
+ * whole batch's kernels for G steps). */
 int dpsnn_batch_step(dpsnn_batch *batch, uint32_t n_steps);
 /* Sums of the members' counters; per-kernel timers of the batch's launches. */
 int dpsnn_batch_get_stats(dpsnn_batch *batch, dpsnn_stats *stats);

@@ -242,6 +242,14 @@ void* dev_alloc(const dpsnn_device& dev, hipStream_t stream, size_t bytes,
 }
 
 void release_launch_set_host(LaunchSet& L) {
+    if (L.graph) {
+        (void)hipGraphExecDestroy(L.graph);
+        L.graph = nullptr;
+    }
+    if (L.cap_stream) {
+        (void)hipStreamDestroy(L.cap_stream);
+        L.cap_stream = nullptr;
+    }
     if (L.ev_copied) {
         if (L.copy_pending) (void)hipEventSynchronize(L.ev_copied);
         (void)hipEventDestroy(L.ev_copied);
@@ -393,6 +401,10 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
         case 7:
             tn.fuse = value;
             return DPSNN_OK;
+        case 8:
+            if (value > 1024) return fail(DPSNN_E_INVAL, "graph steps must be 0 (off) to 1024");
+            tn.graph = value;
+            return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");
     }
@@ -400,7 +412,7 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
 
 // Online autotuner: each candidate shape runs `steps` steps (two interleaved
 // rounds).  With LTP and delivery fused (the default) a candidate is one
-// workgroup size for both plus the delivery unroll, judged by their combined
+// workgroup size for both plus the delivery unroll, ranked by their combined
 // time; with fusion off the fastest delivery shape and the fastest LTP
 // workgroup size are kept separately.
 int autotune(LaunchSet& L, Tuning& tn, Timers& tm, hipStream_t stream, Net* const* m, uint32_t steps) {
@@ -685,7 +697,7 @@ int dpsnn_step(dpsnn_net* h, uint32_t n_steps) {
         n->desc_dirty = false;
     }
     Net* one[1] = {n};
-    for (uint32_t s = 0; s < n_steps; ++s) DPSNN_HIP(launch_step_set(n->solo, n->tune, n->timers, n->stream, one));
+    DPSNN_HIP(launch_steps(n->solo, n->tune, n->timers, n->stream, one, n_steps));
     return DPSNN_OK;
 }
 
@@ -852,6 +864,7 @@ int dpsnn_get_stats(dpsnn_net* h, dpsnn_stats* st) {
     }
     st->steps = n->t;
     st->consolidations = n->consolidations;
+    st->graph_steps = n->graph_steps;
     n->timers.collect();
     st->ms_ltp = n->timers.ms[0]; st->ms_deliver = n->timers.ms[1];
     st->ms_neuron = n->timers.ms[2]; st->ms_wupdate = n->timers.ms[3];
@@ -996,8 +1009,7 @@ int dpsnn_batch_step(dpsnn_batch* b, uint32_t n_steps) {
     // members' descriptors cannot change while they are in the batch (their
     // stimulus is fixed), so the tables uploaded at creation stay valid
     DPSNN_HIP(hipSetDevice(b->dev.device));
-    for (uint32_t s = 0; s < n_steps; ++s)
-        DPSNN_HIP(launch_step_set(b->L, b->tune, b->timers, b->stream, b->members.data()));
+    DPSNN_HIP(launch_steps(b->L, b->tune, b->timers, b->stream, b->members.data(), n_steps));
     return DPSNN_OK;
 }
 
@@ -1014,6 +1026,7 @@ int dpsnn_batch_get_stats(dpsnn_batch* b, dpsnn_stats* st) {
         st->ltp_visits += one.ltp_visits;
         st->consolidations += one.consolidations;
         st->events_exc += one.events_exc;
+        st->graph_steps += one.graph_steps;
     }
     b->timers.collect();
     st->ms_ltp = b->timers.ms[0]; st->ms_deliver = b->timers.ms[1];

@@ -26,6 +26,7 @@ struct Tuning {
     uint32_t parts = 0;           // workgroups per column (0: chosen per launch set)
     uint32_t ltp_stage = 2;       // LDS source spike history in LTP: 0, 1, 2 auto (0 / 1)
     uint32_t fuse = 0xFFFFFFFFu;  // LTP + delivery as one kernel up to this many workgroups each
+    uint32_t graph = 8;           // steps per captured graph; 0 = every step launched directly
     size_t max_lds = 65536;
 };
 
@@ -67,7 +68,13 @@ struct LaunchSet {
     bool copy_pending = false;
     uint64_t steps = 0, copy_steps = 0, base_steps = 0, base_count = 0;
     double per_col = 0.0;
-    // host copies of the uploaded tables
+    // captured graph of graph_steps steps (launch shapes graph_tune), and the
+    // stream it was captured on
+    hipGraphExec_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+    uint32_t graph_steps = 0;
+    Tuning graph_tune;
+    // host copies of the uploaded tables (t0 mirrors the device descriptors)
     std::vector<NetDesc> host_descs;
     std::vector<uint2> host_col, host_neu;
     std::vector<std::vector<uint2>> host_wu;
@@ -138,6 +145,7 @@ struct Net {
 
     // host mirrors
     uint64_t consolidations = 0;
+    uint64_t graph_steps = 0;     // steps run as replays of a captured graph
     uint32_t thal_whole = 0, thal_thr = 0;
 
     Tuning tune;
@@ -168,6 +176,9 @@ hipError_t launch_build(Net& n);
 // One step of every network of the set; members[k] is the network of slot k.
 hipError_t launch_step_set(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
                            Net* const* members);
+// n_steps steps of the set, runs of tune.graph steps as captured graphs.
+hipError_t launch_steps(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
+                        Net* const* members, uint32_t n_steps);
 hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, float* Pf, uint32_t* tgt_out,
                             uint8_t* dly_out, float* w_out, float* P_out, float* D_out);
 hipError_t launch_scatter_P(Net& n, float* Pf);

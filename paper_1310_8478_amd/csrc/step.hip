@@ -10,11 +10,13 @@
 //              accumulate the currents of the reachable target columns in an
 //              LDS window, apply LTD, then flush the window.
 //   k_neuron   item 2.7 plus the thalamic input: Izhikevich update with two
-//              0.5 ms sub-steps, threshold and reset, spike history, the
-//              raster word of each wavefront written with one ballot, and
-//              the clock advanced by the network's last workgroup.
+//              0.5 ms sub-steps, threshold and reset, spike history, and the
+//              raster word of each wavefront written with one ballot.
 //   k_wupdate, k_wupdate_fwd  every weight_update_period steps: fold P - D
 //              into the weights.
+// Every kernel reads its network's step as t = t0 + tstep: t0 from the
+// network's descriptor, tstep a launch argument.  k_rebase moves t0 forward,
+// which lets one captured graph of G steps be replayed at any step.
 #include "net.h"
 
 namespace dpsnn {
@@ -940,6 +942,12 @@ __global__ __launch_bounds__(256) void k_wupdate(const NetDesc* __restrict__ nds
     }
 }
 
+// t0 += delta for each of the K descriptors of a launch set
+__global__ __launch_bounds__(64) void k_rebase(NetDesc* __restrict__ nds, uint32_t K, uint32_t delta) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < K) nds[k].t0 += delta;
+}
+
 __global__ __launch_bounds__(256) void k_wupdate_fwd(const NetDesc* __restrict__ nds) {
     const NetDesc& nd = *nds;
     const Dims d = nd.d;
@@ -1135,7 +1143,7 @@ void sample_regime(LaunchSet& L, hipStream_t stream, Net* const* members) {
         L.base_steps = L.copy_steps;
         L.copy_pending = false;
     }
-    if (!L.copy_pending && L.steps % 8u == 0u) {
+    if (!L.copy_pending && L.steps - L.copy_steps >= 8u) {
         if (hipMemcpyAsync(L.ev_host, L.ev_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            stream) == hipSuccess &&
             hipEventRecord(L.ev_copied, stream) == hipSuccess) {
@@ -1161,21 +1169,22 @@ Tuning effective_tuning(const LaunchSet& L, const Tuning& tune) {
     return t;
 }
 
-// One step of every network of the set, in the paper's loop order: LTP,
-// delivery (+ currents and LTD), neuron update, consolidation where due, and
-// the clock advance.  Timer kinds: 0 LTP, 1 delivery, 2 neuron, 3 consolidation.
-hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipStream_t stream,
-                           Net* const* members) {
+namespace {
+
+bool same_shapes(const Tuning& a, const Tuning& b) {
+    return a.deliver_block == b.deliver_block && a.ltp_block == b.ltp_block && a.window == b.window &&
+           a.unroll == b.unroll && a.age == b.age && a.parts == b.parts && a.ltp_stage == b.ltp_stage &&
+           a.fuse == b.fuse && a.max_lds == b.max_lds;
+}
+
+// The kernels of one step of every network of the set at t = t0 + tstep, in
+// the paper's loop order: LTP, delivery (+ currents and LTD), neuron update,
+// and consolidation for the members flagged in `wu`.  `spikes`: some member
+// is past its first step.  Changes no host state except the timers.  Timer
+// kinds: 0 LTP, 1 delivery, 2 neuron, 3 consolidation.
+hipError_t enqueue_step(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
+                        Net* const* members, uint32_t tstep, bool any_spikes, const uint8_t* wu) {
     hipError_t e;
-    const Tuning tune = effective_tuning(L, tune_in);
-    // every member has advanced by the same number of steps since the set was
-    // made; the kernels read t = t0 + tstep
-    if (L.K == 0) return hipSuccess;
-    const uint32_t tstep = members[0]->t - L.host_descs[0].t0;
-    for (uint32_t k = 1; k < L.K; ++k)
-        if (members[k]->t - L.host_descs[k].t0 != tstep) return hipErrorInvalidValue;
-    bool any_spikes = false;
-    for (uint32_t k = 0; k < L.K; ++k) any_spikes |= members[k]->t >= 1;
     if (any_spikes) {
         const uint32_t BS = std::max<uint32_t>(tune.ltp_block, ((L.max_w + 63) / 64) * 64);
         const size_t base = ((size_t)2 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
@@ -1203,8 +1212,6 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipS
                     : launch_deliver<uint32_t>(L, tune, stream, members, nparts, tstep, fl);
         tm.end(stream);
         if (e != hipSuccess) return e;
-        L.steps++;
-        sample_regime(L, stream, members);
     }
     tm.begin(2, stream);
     if (L.sum_mode == DPSNN_SUM_FIXED)
@@ -1215,20 +1222,140 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipS
         hipLaunchKernelGGL(k_neuron<DPSNN_SUM_ORDERED>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu, tstep);
     tm.end(stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    for (uint32_t k = 0; k < L.K; ++k) {
-        Net& n = *members[k];
-        const uint32_t Tw = n.cfg.weight_update_period;
-        if (Tw && (n.t + 1) % Tw == 0 && n.S_exc && L.n_wu[k]) {
-            tm.begin(3, stream);
-            hipLaunchKernelGGL(k_wupdate, dim3(L.n_wu[k]), dim3(256), 0, stream, L.descs + k, L.bmap_wu[k]);
-            const uint64_t nfwd = ((uint64_t)n.S + 256ull * kWupdateItems - 1) / (256ull * kWupdateItems);
-            hipLaunchKernelGGL(k_wupdate_fwd, dim3((uint32_t)nfwd), dim3(256), 0, stream, L.descs + k);
-            tm.end(stream);
-            n.consolidations++;
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
+    for (uint32_t k = 0; wu && k < L.K; ++k) {
+        if (!wu[k]) continue;
+        const Net& n = *members[k];
+        tm.begin(3, stream);
+        hipLaunchKernelGGL(k_wupdate, dim3(L.n_wu[k]), dim3(256), 0, stream, L.descs + k, L.bmap_wu[k]);
+        const uint64_t nfwd = ((uint64_t)n.S + 256ull * kWupdateItems - 1) / (256ull * kWupdateItems);
+        hipLaunchKernelGGL(k_wupdate_fwd, dim3((uint32_t)nfwd), dim3(256), 0, stream, L.descs + k);
+        tm.end(stream);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    for (uint32_t k = 0; k < L.K; ++k) members[k]->t += 1;
+    return hipSuccess;
+}
+
+// Steps until member n's next consolidation (0: due in its current step).
+uint32_t steps_to_consolidation(const LaunchSet& L, const Net& n, uint32_t k) {
+    const uint32_t Tw = n.cfg.weight_update_period;
+    if (!Tw || !n.S_exc || !L.n_wu[k]) return 0xFFFFFFFFu;
+    const uint32_t r = (n.t + 1u) % Tw;
+    return r == 0 ? 0u : Tw - r;
+}
+
+// Step offset common to the members (t - t0); false if they disagree.
+bool set_tstep(const LaunchSet& L, Net* const* members, uint32_t& tstep) {
+    tstep = members[0]->t - L.host_descs[0].t0;
+    for (uint32_t k = 1; k < L.K; ++k)
+        if (members[k]->t - L.host_descs[k].t0 != tstep) return false;
+    return true;
+}
+
+// Steps [t, t + G) of every member as one captured graph, replayed on
+// `stream`.  The graph holds the G steps' kernels at tstep 0 .. G-1 followed
+// by k_rebase(G), so it starts from descriptors with t0 = t: a set whose
+// offset is not 0 is rebased first.  It is captured again when G or the
+// launch shapes change.  Only steps without consolidation and past the first
+// are graphed; there are no memory-set nodes.
+hipError_t launch_graph(LaunchSet& L, const Tuning& tune, hipStream_t stream, Net* const* members,
+                        uint32_t G) {
+    hipError_t e;
+    uint32_t tstep;
+    if (!set_tstep(L, members, tstep)) return hipErrorInvalidValue;
+    if (L.graph && (L.graph_steps != G || !same_shapes(L.graph_tune, tune))) {
+        (void)hipGraphExecDestroy(L.graph);
+        L.graph = nullptr;
+    }
+    if (tstep) {
+        hipLaunchKernelGGL(k_rebase, dim3((L.K + 63u) / 64u), dim3(64), 0, stream, L.descs, L.K, tstep);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        for (uint32_t k = 0; k < L.K; ++k) L.host_descs[k].t0 += tstep;
+    }
+    if (!L.graph) {
+        if (!L.cap_stream && (e = hipStreamCreateWithFlags(&L.cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return e;
+        if ((e = hipStreamBeginCapture(L.cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess) return e;
+        Timers off;
+        hipError_t ce = hipSuccess;
+        for (uint32_t j = 0; j < G && ce == hipSuccess; ++j)
+            ce = enqueue_step(L, tune, off, L.cap_stream, members, j, true, nullptr);
+        if (ce == hipSuccess) {
+            hipLaunchKernelGGL(k_rebase, dim3((L.K + 63u) / 64u), dim3(64), 0, L.cap_stream, L.descs, L.K, G);
+            ce = hipGetLastError();
+        }
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(L.cap_stream, &g);  // always ends the capture
+        if (ce == hipSuccess) ce = e;
+        if (ce == hipSuccess) ce = hipGraphInstantiate(&L.graph, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (ce != hipSuccess) {
+            L.graph = nullptr;
+            return ce;
+        }
+        L.graph_steps = G;
+        L.graph_tune = tune;
+    }
+    if ((e = hipGraphLaunch(L.graph, stream)) != hipSuccess) return e;
+    for (uint32_t k = 0; k < L.K; ++k) {
+        L.host_descs[k].t0 += G;
+        members[k]->t += G;
+        members[k]->graph_steps += G;
+    }
+    L.steps += G;
+    sample_regime(L, stream, members);
+    return hipSuccess;
+}
+
+}  // namespace
+
+// One step, launched directly (see enqueue_step), and the host bookkeeping:
+// regime sample, consolidation count, clock.
+hipError_t launch_step_set(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipStream_t stream,
+                           Net* const* members) {
+    if (L.K == 0) return hipSuccess;
+    const Tuning tune = effective_tuning(L, tune_in);
+    // every member has advanced by the same number of steps since its
+    // descriptor's t0 was set; the kernels read t = t0 + tstep
+    uint32_t tstep;
+    if (!set_tstep(L, members, tstep)) return hipErrorInvalidValue;
+    bool any_spikes = false;
+    for (uint32_t k = 0; k < L.K; ++k) any_spikes |= members[k]->t >= 1;
+    std::vector<uint8_t> wu(L.K);
+    for (uint32_t k = 0; k < L.K; ++k) wu[k] = steps_to_consolidation(L, *members[k], k) == 0;
+    hipError_t e = enqueue_step(L, tune, tm, stream, members, tstep, any_spikes, wu.data());
+    if (e != hipSuccess) return e;
+    if (any_spikes) {
+        L.steps++;
+        sample_regime(L, stream, members);
+    }
+    for (uint32_t k = 0; k < L.K; ++k) {
+        if (wu[k]) members[k]->consolidations++;
+        members[k]->t += 1;
+    }
+    return hipSuccess;
+}
+
+// n_steps steps: runs of tune.graph steps that need no consolidation, no
+// timers and no first step are replayed as captured graphs, the rest are
+// launched one by one.  The results are the same either way.
+hipError_t launch_steps(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipStream_t stream,
+                        Net* const* members, uint32_t n_steps) {
+    const uint32_t G = tune_in.graph;
+    uint32_t s = 0;
+    while (s < n_steps) {
+        bool graphed = G && n_steps - s >= G && !tm.on && L.K && L.sum_mode != DPSNN_SUM_ORDERED;
+        for (uint32_t k = 0; graphed && k < L.K; ++k)
+            graphed = members[k]->t >= 1 && steps_to_consolidation(L, *members[k], k) >= G;
+        hipError_t e;
+        if (graphed) {
+            e = launch_graph(L, effective_tuning(L, tune_in), stream, members, G);
+            s += G;
+        } else {
+            e = launch_step_set(L, tune_in, tm, stream, members);
+            s += 1;
+        }
+        if (e != hipSuccess) return e;
+    }
     return hipSuccess;
 }
 

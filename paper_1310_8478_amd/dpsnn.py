@@ -56,7 +56,7 @@ class dpsnn_stats(C.Structure):
         ("ms_ltp", C.c_double), ("ms_deliver", C.c_double), ("ms_neuron", C.c_double),
         ("ms_wupdate", C.c_double),
         ("n_ltp", C.c_uint64), ("n_deliver", C.c_uint64), ("n_neuron", C.c_uint64),
-        ("n_wupdate", C.c_uint64),
+        ("n_wupdate", C.c_uint64), ("graph_steps", C.c_uint64),
     ]
 
 
