@@ -310,6 +310,29 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
             return wa > wb;
         });
     }
+    // one network: workgroup i runs on XCD i mod 8 (round-robin dispatch), and
+    // each XCD has its own L2.  XCD x gets the x-th eighth of the columns in
+    // row-major order, walked column by column, so that the columns in flight
+    // on one XCD form a compact block whose reachable neighbourhoods overlap
+    // in its L2 (a few per cent faster on grids of 1024 columns and more)
+    if (cnt == 1 && col.size() >= 64) {
+        const uint32_t C = (uint32_t)col.size(), gx = m[0]->d.GX;
+        std::vector<std::vector<uint32_t>> part(kXcds);
+        for (uint32_t x = 0; x < kXcds; ++x) {
+            const uint32_t a = (uint32_t)((uint64_t)C * x / kXcds);
+            const uint32_t b = (uint32_t)((uint64_t)C * (x + 1) / kXcds);
+            for (uint32_t c = a; c < b; ++c) part[x].push_back(c);
+            std::stable_sort(part[x].begin(), part[x].end(), [&](uint32_t p, uint32_t q) {
+                return p % gx != q % gx ? p % gx < q % gx : p / gx < q / gx;
+            });
+        }
+        col.clear();
+        size_t pos[kXcds] = {};
+        for (size_t i = 0; col.size() < C; ++i) {
+            const uint32_t x = (uint32_t)(i % kXcds);
+            if (pos[x] < part[x].size()) col.push_back(make_uint2(0u, part[x][pos[x]++]));
+        }
+    }
     L.n_col = (uint32_t)col.size();
     L.n_neu = (uint32_t)neu.size();
     {

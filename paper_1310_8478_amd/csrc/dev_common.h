@@ -224,7 +224,7 @@ __device__ __forceinline__ unsigned long long block_sum64(unsigned long long v, 
 // neighbouring words decide whether a run continues across the word edge;
 // `split` (0 < split < Ncol) forces a run boundary between split-1 and split.
 struct WordRuns {
-    unsigned long long starts, ends;
+    unsigned long long starts, ends, word;
 };
 
 __device__ __forceinline__ WordRuns word_runs(const uint64_t* __restrict__ words, uint32_t W,
@@ -233,6 +233,7 @@ __device__ __forceinline__ WordRuns word_runs(const uint64_t* __restrict__ words
     const unsigned long long prev_top = (w > 0) ? (words[w - 1] >> 63) : 0ull;
     const unsigned long long next_low = (w + 1 < W) ? (words[w + 1] & 1ull) : 0ull;
     WordRuns r;
+    r.word = m;
     r.starts = m & ~((m << 1) | prev_top);
     r.ends = m & ~((m >> 1) | (next_low << 63));
     if (split > 0) {

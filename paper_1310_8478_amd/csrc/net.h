@@ -13,6 +13,8 @@
 
 namespace dpsnn {
 
+constexpr uint32_t kXcds = 8;  // accelerator dies (XCDs) of the GPU, each with its own L2
+
 // Launch-shape knobs; results never depend on them.  "Auto" values follow the
 // launch set's measured regime: sparse (at least 2048 columns, and a source
 // column delivers fewer events per step than its current window has entries)

@@ -62,21 +62,23 @@ __device__ __forceinline__ void ltp_body(const NetDesc* __restrict__ nds,
     const uint32_t ct = br.y;
     const uint64_t* words = ring + ((size_t)(t % d.R) * d.C + ct) * d.W;
 
-    WordRuns wr{0ull, 0ull};
+    // the column's raster words and the small tables, loaded together
+    WordRuns wr{0ull, 0ull, 0ull};
     if (tid < d.W) wr = word_runs(words, d.W, tid, 0u);
-    const uint32_t cs = (uint32_t)__popcll(wr.starts);
-    const uint32_t ce = (uint32_t)__popcll(wr.ends);
-    const uint32_t nsp_local = (tid < d.W) ? (uint32_t)__popcll(words[tid]) : 0u;
-    uint32_t nsp;
-    (void)block_scan(nsp_local, sh, nsp);
-    if (nsp == 0) return;  // block-uniform
-    // the k-th run starts at the k-th start bit and ends at the k-th end bit
-    // of the column (runs may span words)
-    uint32_t nruns, nends;
-    const uint32_t bs_ = block_scan(cs, sh, nruns);
-    const uint32_t be_ = block_scan(ce, sh, nends);
     if (tid < kSlots) smap[tid] = srcmap[ct * kSlots + tid];
     if (tid < 64) tph[tid] = tid < tp_len ? tp[tid] : 0.0f;
+    const uint32_t cs = (uint32_t)__popcll(wr.starts);
+    const uint32_t ce = (uint32_t)__popcll(wr.ends);
+    uint32_t nsp;
+    (void)block_scan((uint32_t)__popcll(wr.word), sh, nsp);
+    if (nsp == 0) return;  // block-uniform
+    // the k-th run starts at the k-th start bit and ends at the k-th end bit
+    // of the column (runs may span words); starts and ends are counted in one
+    // scan (at most 32 of each per word and 1024 words: each half < 2^16)
+    uint32_t tot;
+    const uint32_t pre = block_scan(cs | (ce << 16), sh, tot);
+    uint32_t nruns = tot & 0xFFFFu;
+    const uint32_t bs_ = pre & 0xFFFFu, be_ = pre >> 16;
     // stage the 13 source columns' history when the expected visits (spiking
     // targets x about 0.8 M incoming excitatory synapses each) outnumber it
     const bool stage = allow_stage && nparts == 1u &&
@@ -331,10 +333,21 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     }
     if (tid < kSlots) cmap[tid] = colmap[c * kSlots + tid];
     if (tid < 64) tmh[tid] = tid < tm_len ? tm[tid] : 0.0f;
-    __syncthreads();
 
     const long long q_inh = to_fixed(d.w_inh);
     const uint32_t split = (d.Ne > 0 && d.Ne < d.Ncol) ? d.Ne : 0u;
+    // tasks (delay, raster word) are taken a whole number of delays at a time
+    // (the host keeps W <= BS), so that no run is split between two chunks;
+    // this thread's word of the first chunk is loaded here, together with the
+    // tables above, and serves both the all-firing test and the run decoding
+    const uint32_t dpc = max(1u, BS / d.W);
+    const uint32_t nd0 = min(dpc, d.Dmax);
+    const int64_t s0 = (int64_t)t - (int64_t)(1u + tid / d.W) + 1;
+    const bool live0 = tid < nd0 * d.W && s0 >= 1;
+    WordRuns wr0{0ull, 0ull, 0ull};
+    if (live0)
+        wr0 = word_runs(ring + ((size_t)((uint64_t)s0 % d.R) * d.C + c) * d.W, d.W,
+                        tid - (tid / d.W) * d.W, split);
     unsigned long long ev_local = 0, exc_events = 0;  // this thread's deliveries
     bool staged = false;
     // the column's inhibitory synapses (all of delay 1) form one forward range
@@ -389,11 +402,13 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
         const unsigned long long last = tail >= 64u ? ~0ull : ((1ull << tail) - 1ull);
         for (uint32_t x = tid; x < d.Dmax * d.W; x += BS) {
             const uint32_t dd = x / d.W + 1u, wd = x - (dd - 1u) * d.W;
-            const uint64_t word =
-                ring[((size_t)((t - dd + 1u) % d.R) * d.C + c) * d.W + wd];
+            const uint64_t word = (x == tid && live0)
+                                      ? wr0.word
+                                      : ring[((size_t)((t - dd + 1u) % d.R) * d.C + c) * d.W + wd];
             if (word != (wd + 1u == d.W ? last : ~0ull)) full = 0;
         }
     }
+    __syncthreads();
     full = __syncthreads_and(full);
     if (full) {
         const uint32_t c0 = c * d.Ncol * d.M;
@@ -485,144 +500,146 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
             if (na < wr_.end) load(na, A);
             if (nb < wr_.end) process(B);
         }
-    }
-
-    // tasks (delay, raster word), processed a whole number of delays at a
-    // time so that no run is split between two chunks (the host keeps W <= BS)
-    const uint32_t dpc = max(1u, BS / d.W);
-    for (uint32_t d0 = 1; !full && d0 <= d.Dmax; d0 += dpc) {
-        const uint32_t nd = min(dpc, d.Dmax - d0 + 1u);
-        const uint32_t dd = d0 + tid / d.W;
+    } else {
+        // not all firing: decode the spiking runs, a chunk of delays at a time
         const uint32_t wd = tid - (tid / d.W) * d.W;
-        const int64_t s = (int64_t)t - (int64_t)dd + 1;
-        const bool live = tid < nd * d.W && s >= 1;
-        WordRuns wr{0ull, 0ull};
-        if (live) {
-            const uint64_t* words = ring + ((size_t)((uint64_t)s % d.R) * d.C + c) * d.W;
-            wr = word_runs(words, d.W, wd, split);
-        }
-        const uint32_t cs = (uint32_t)__popcll(wr.starts);
-        const uint32_t ce = (uint32_t)__popcll(wr.ends);
-        uint32_t nruns, nends;
-        const uint32_t bs_ = block_scan(cs, sh, nruns);
-        const uint32_t be_ = block_scan(ce, sh, nends);
-        for (uint32_t r0 = 0; r0 < nruns; r0 += BS) {
-            // k-th start / k-th end of the chunk form run k (runs never cross a delay)
-            {
-                unsigned long long m = wr.starts;
-                for (uint32_t k = 0; k < cs; ++k) {
-                    const uint32_t idx = bs_ + k;
-                    const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
-                    m &= m - 1ull;
-                    if (idx >= r0 && idx < r0 + BS) {
-                        pos0[idx - r0] = wd * 64u + b;
-                        excf[idx - r0] = dd;
+        WordRuns wr = wr0;  // this thread's word of the current chunk
+        for (uint32_t d0 = 1; d0 <= d.Dmax; d0 += dpc) {
+            const uint32_t dd = d0 + tid / d.W;
+            // starts and ends counted in one scan: at most 32 of each per word
+            // and at most 1024 words, so neither half reaches 2^16
+            const uint32_t cs = (uint32_t)__popcll(wr.starts);
+            const uint32_t ce = (uint32_t)__popcll(wr.ends);
+            uint32_t tot;
+            const uint32_t pre = block_scan(cs | (ce << 16), sh, tot);
+            const uint32_t nruns = tot & 0xFFFFu;
+            const uint32_t bs_ = pre & 0xFFFFu, be_ = pre >> 16;
+            for (uint32_t r0 = 0; r0 < nruns; r0 += BS) {
+                // k-th start / k-th end of the chunk form run k (runs never cross a delay)
+                {
+                    unsigned long long m = wr.starts;
+                    for (uint32_t k = 0; k < cs; ++k) {
+                        const uint32_t idx = bs_ + k;
+                        const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
+                        m &= m - 1ull;
+                        if (idx >= r0 && idx < r0 + BS) {
+                            pos0[idx - r0] = wd * 64u + b;
+                            excf[idx - r0] = dd;
+                        }
+                    }
+                    m = wr.ends;
+                    for (uint32_t k = 0; k < ce; ++k) {
+                        const uint32_t idx = be_ + k;
+                        const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
+                        m &= m - 1ull;
+                        if (idx >= r0 && idx < r0 + BS) pref[idx - r0] = wd * 64u + b + 1u;
                     }
                 }
-                m = wr.ends;
-                for (uint32_t k = 0; k < ce; ++k) {
-                    const uint32_t idx = be_ + k;
-                    const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
-                    m &= m - 1ull;
-                    if (idx >= r0 && idx < r0 + BS) pref[idx - r0] = wd * 64u + b + 1u;
+                __syncthreads();
+                const uint32_t nr = min(BS, nruns - r0);
+                // run -> its forward range [a, e) and the aligned quads over it
+                uint32_t a = 0, e = 0, nq = 0;
+                if (tid < nr) {
+                    const uint32_t le = min(pref[tid], d.Ncol);
+                    const uint32_t ls = min(pos0[tid], le);
+                    const uint32_t rd = min(max(excf[tid], 1u), d.Dmax);
+                    const size_t sb = (size_t)c * d.segs + (size_t)(rd - 1u) * d.Ncol;
+                    a = seg_off[sb + ls];
+                    e = max(a, seg_off[sb + le]);
+                    nq = e > a ? ((e + 3u) >> 2) - (a >> 2) : 0u;
                 }
-            }
-            __syncthreads();
-            const uint32_t nr = min(BS, nruns - r0);
-            // run -> its forward range [a, e) and the aligned quads over it
-            uint32_t a = 0, e = 0, nq = 0;
-            if (tid < nr) {
-                const uint32_t le = min(pref[tid], d.Ncol);
-                const uint32_t ls = min(pos0[tid], le);
-                const uint32_t rd = min(max(excf[tid], 1u), d.Dmax);
-                const size_t sb = (size_t)c * d.segs + (size_t)(rd - 1u) * d.Ncol;
-                a = seg_off[sb + ls];
-                e = max(a, seg_off[sb + le]);
-                nq = e > a ? ((e + 3u) >> 2) - (a >> 2) : 0u;
-            }
-            __syncthreads();
-            uint32_t Q;
-            const uint32_t qx = block_scan(nq, sh, Q);
-            if (tid < nr) {
-                pos0[tid] = a;
-                excf[tid] = e;
-                pref[tid] = qx;
-            }
-            uint32_t qlo, qhi;
-            part_slice(Q, part, nparts, qlo, qhi);
-            if (allow_age && !staged && 4u * (qhi - qlo) >= nwin) {  // block-uniform
-                for (uint32_t x = tid; x < nwin; x += BS) {
-                    const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
-                    const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
-                    const int64_t ag = (tq == kNoSpike) ? 255 : (int64_t)t - tq;
-                    age[x] = (uint8_t)(ag < 255 ? ag : 255);
+                __syncthreads();
+                uint32_t Q;
+                const uint32_t qx = block_scan(nq, sh, Q);
+                if (tid < nr) {
+                    pos0[tid] = a;
+                    excf[tid] = e;
+                    pref[tid] = qx;
                 }
-                staged = true;
-            }
-            __syncthreads();
-            // each lane takes one quad of positions p .. p+3 of a run at a time
-            // (vector loads; bit j of the mask: p + j lies in the run)
-            constexpr int QU = U >= 2 ? U / 2 : 1;
-            const WaveRange wr_ = wave_range_in(qlo, qhi);
-            uint32_t cur = wr_.begin < wr_.end ? upper_run(pref, 0u, nr, wr_.begin) : 0u;
-            for (uint32_t kb = wr_.begin; kb < wr_.end; kb += 64u * QU) {
-                uint32_t p4[QU], m4[QU], ti[QU][4];
-                bool ex4[QU];
-                float4 wv[QU], dv[QU];
-#pragma unroll
-                for (int q = 0; q < QU; ++q) {
-                    const uint32_t sb = kb + q * 64u;
-                    const uint32_t k = sb + lane_id();
-                    const bool ok = k < wr_.end;
-                    if (sb < wr_.end && cur + 1 < nr && pref[cur + 1] <= sb)
-                        cur = upper_run(pref, cur + 1, nr, sb);
-                    const uint32_t r = ok ? lane_run(pref, cur, nr, k) : 0u;
-                    const uint32_t ra = pos0[r], re = excf[r];
-                    const uint32_t p = ok ? ((ra >> 2) + (k - pref[r])) << 2 : 0u;
-                    uint32_t m = 0;
-#pragma unroll
-                    for (uint32_t j = 0; j < 4; ++j) m |= (ok && p + j >= ra && p + j < re) ? (1u << j) : 0u;
-                    p4[q] = p;
-                    m4[q] = m;
-                    ex4[q] = m && is_exc(ra);
-                }
-#pragma unroll
-                for (int q = 0; q < QU; ++q) {
-                    if (sizeof(TgtT) == 2) {
-                        const uint2 tv = m4[q] ? *(const uint2*)(tgt + p4[q]) : make_uint2(0u, 0u);
-                        ti[q][0] = tv.x & 0xFFFFu; ti[q][1] = tv.x >> 16;
-                        ti[q][2] = tv.y & 0xFFFFu; ti[q][3] = tv.y >> 16;
-                    } else {
-                        const uint4 tv = m4[q] ? *(const uint4*)((const uint32_t*)tgt + p4[q])
-                                               : make_uint4(0u, 0u, 0u, 0u);
-                        ti[q][0] = tv.x; ti[q][1] = tv.y; ti[q][2] = tv.z; ti[q][3] = tv.w;
+                uint32_t qlo, qhi;
+                part_slice(Q, part, nparts, qlo, qhi);
+                if (allow_age && !staged && 4u * (qhi - qlo) >= nwin) {  // block-uniform
+                    for (uint32_t x = tid; x < nwin; x += BS) {
+                        const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
+                        const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
+                        const int64_t ag = (tq == kNoSpike) ? 255 : (int64_t)t - tq;
+                        age[x] = (uint8_t)(ag < 255 ? ag : 255);
                     }
-                    wv[q] = ex4[q] ? *(const float4*)(w + p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
-                    dv[q] = ex4[q] ? *(const float4*)(Dacc + p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    staged = true;
                 }
-#pragma unroll
-                for (int q = 0; q < QU; ++q) {
-                    const uint32_t m = m4[q];
-                    if (!m) continue;
-                    const bool ex = ex4[q];
-                    if (m & 1u) deliver_one(ex, ti[q][0], wv[q].x, dv[q].x);
-                    if (m & 2u) deliver_one(ex, ti[q][1], wv[q].y, dv[q].y);
-                    if (m & 4u) deliver_one(ex, ti[q][2], wv[q].z, dv[q].z);
-                    if (m & 8u) deliver_one(ex, ti[q][3], wv[q].w, dv[q].w);
-                    if (ex) {
-                        // a partial quad may share positions with another run
-                        if (m == 0xFu) {
-                            *(float4*)(Dacc + p4[q]) = dv[q];
+                __syncthreads();
+                // each lane takes one quad of positions p .. p+3 of a run at a time
+                // (vector loads; bit j of the mask: p + j lies in the run)
+                constexpr int QU = U >= 2 ? U / 2 : 1;
+                const WaveRange wr_ = wave_range_in(qlo, qhi);
+                uint32_t cur = wr_.begin < wr_.end ? upper_run(pref, 0u, nr, wr_.begin) : 0u;
+                for (uint32_t kb = wr_.begin; kb < wr_.end; kb += 64u * QU) {
+                    uint32_t p4[QU], m4[QU], ti[QU][4];
+                    bool ex4[QU];
+                    float4 wv[QU], dv[QU];
+    #pragma unroll
+                    for (int q = 0; q < QU; ++q) {
+                        const uint32_t sb = kb + q * 64u;
+                        const uint32_t k = sb + lane_id();
+                        const bool ok = k < wr_.end;
+                        if (sb < wr_.end && cur + 1 < nr && pref[cur + 1] <= sb)
+                            cur = upper_run(pref, cur + 1, nr, sb);
+                        const uint32_t r = ok ? lane_run(pref, cur, nr, k) : 0u;
+                        const uint32_t ra = pos0[r], re = excf[r];
+                        const uint32_t p = ok ? ((ra >> 2) + (k - pref[r])) << 2 : 0u;
+                        uint32_t m = 0;
+    #pragma unroll
+                        for (uint32_t j = 0; j < 4; ++j) m |= (ok && p + j >= ra && p + j < re) ? (1u << j) : 0u;
+                        p4[q] = p;
+                        m4[q] = m;
+                        ex4[q] = m && is_exc(ra);
+                    }
+    #pragma unroll
+                    for (int q = 0; q < QU; ++q) {
+                        if (sizeof(TgtT) == 2) {
+                            const uint2 tv = m4[q] ? *(const uint2*)(tgt + p4[q]) : make_uint2(0u, 0u);
+                            ti[q][0] = tv.x & 0xFFFFu; ti[q][1] = tv.x >> 16;
+                            ti[q][2] = tv.y & 0xFFFFu; ti[q][3] = tv.y >> 16;
                         } else {
-                            if (m & 1u) Dacc[p4[q]] = dv[q].x;
-                            if (m & 2u) Dacc[p4[q] + 1] = dv[q].y;
-                            if (m & 4u) Dacc[p4[q] + 2] = dv[q].z;
-                            if (m & 8u) Dacc[p4[q] + 3] = dv[q].w;
+                            const uint4 tv = m4[q] ? *(const uint4*)((const uint32_t*)tgt + p4[q])
+                                                   : make_uint4(0u, 0u, 0u, 0u);
+                            ti[q][0] = tv.x; ti[q][1] = tv.y; ti[q][2] = tv.z; ti[q][3] = tv.w;
+                        }
+                        wv[q] = ex4[q] ? *(const float4*)(w + p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        dv[q] = ex4[q] ? *(const float4*)(Dacc + p4[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+    #pragma unroll
+                    for (int q = 0; q < QU; ++q) {
+                        const uint32_t m = m4[q];
+                        if (!m) continue;
+                        const bool ex = ex4[q];
+                        if (m & 1u) deliver_one(ex, ti[q][0], wv[q].x, dv[q].x);
+                        if (m & 2u) deliver_one(ex, ti[q][1], wv[q].y, dv[q].y);
+                        if (m & 4u) deliver_one(ex, ti[q][2], wv[q].z, dv[q].z);
+                        if (m & 8u) deliver_one(ex, ti[q][3], wv[q].w, dv[q].w);
+                        if (ex) {
+                            // a partial quad may share positions with another run
+                            if (m == 0xFu) {
+                                *(float4*)(Dacc + p4[q]) = dv[q];
+                            } else {
+                                if (m & 1u) Dacc[p4[q]] = dv[q].x;
+                                if (m & 2u) Dacc[p4[q] + 1] = dv[q].y;
+                                if (m & 4u) Dacc[p4[q] + 2] = dv[q].z;
+                                if (m & 8u) Dacc[p4[q] + 3] = dv[q].w;
+                            }
                         }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
+            // the next chunk's word
+            const uint32_t d1 = d0 + dpc;
+            if (d1 <= d.Dmax) {
+                const int64_t s1 = (int64_t)t - (int64_t)(d1 + tid / d.W) + 1;
+                wr = WordRuns{0ull, 0ull, 0ull};
+                if (tid < min(dpc, d.Dmax - d1 + 1u) * d.W && s1 >= 1)
+                    wr = word_runs(ring + ((size_t)((uint64_t)s1 % d.R) * d.C + c) * d.W, d.W, wd, split);
+            }
         }
     }
     if (WINDOW) {

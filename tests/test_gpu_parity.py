@@ -333,3 +333,18 @@ def test_mid_full_size_window_bitexact(dp, orc):
         np.testing.assert_array_equal(bits(ws["D"]), bits(s["D"]))
         np.testing.assert_array_equal(bits(ws["P"]), bits(s["P"]))
     n.close()
+
+
+@pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
+def test_many_columns_bitexact(dp, orc, mode):
+    # 77 columns (eighths of 9 and 10): a single network of 64 columns or more
+    # is dispatched in an XCD-aware column order
+    cfg = W.make_config(grid_x=11, grid_y=7, neurons_per_column=60, synapses_per_neuron=30,
+                        thalamic_rate=3.0, w_exc_init=9.0, weight_update_period=70,
+                        sum_mode=mode, seed=7707)
+    T = 160
+    _say(f"11x7 grid, mode {mode}")
+    g = gpu_run(dp, cfg, T)
+    o = oracle_run(orc, cfg, T)
+    assert_bitexact(g, o)
+    assert len(o["tt"]) > 1000
