@@ -51,7 +51,10 @@ extern "C" {
  * sum of currents arriving in one step; Sec. 2, "Projection of synapses"). */
 #define DPSNN_SUM_ORDERED 0u  /* fp32 left fold: thalamic picks, stimulus list,
                                  then deliveries by (delay, source id, synapse j) */
-#define DPSNN_SUM_ATOMIC  1u  /* fp32, unordered atomics: not bit-reproducible */
+#define DPSNN_SUM_ATOMIC  1u  /* fp32, unordered atomics: not bit-reproducible
+                                 (a source column's contributions to one target
+                                 are summed exactly, then rounded to fp32 once
+                                 and added with an atomic in arbitrary order) */
 #define DPSNN_SUM_FIXED   2u  /* each term rounded to a multiple of 2^-32, summed
                                  exactly in int64, the total rounded once to fp32 */
 
