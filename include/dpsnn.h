@@ -127,7 +127,10 @@ int dpsnn_footprint_bytes(const dpsnn_config *cfg, uint64_t *bytes);
  * connections"): every synapse is drawn from a counter-based generator keyed
  * by (seed) with counter (id, j), so the network does not depend on launch
  * shapes.  On success *out owns all device state; the call returns after the
- * build has completed on the stream. */
+ * build has completed on the stream.  Size limits (DPSNN_E_INVAL beyond
+ * them): fewer than 2^26 neurons, fewer than 2^36 synapses (2^32 with
+ * DPSNN_SUM_ORDERED), and 13 x neurons_per_column x synapses_per_neuron
+ * below 2^31. */
 int dpsnn_build_network(const dpsnn_config *cfg, const dpsnn_device *dev, dpsnn_net **out);
 
 /* Enqueue n_steps 1 ms steps (Sec. 2, loop items 2.1-2.7, plus the periodic

@@ -65,7 +65,14 @@ int validate(const dpsnn_config* c, Derived* o) {
     const uint64_t N = C * Ncol;
     if (N >= (1ull << 26)) return fail(DPSNN_E_INVAL, "at most 2^26 - 1 neurons per network");
     const uint64_t S = N * c->synapses_per_neuron;
-    if (S >= (1ull << 32)) return fail(DPSNN_E_INVAL, "at most 2^32 - 1 synapses per network");
+    if (S >= (1ull << 36)) return fail(DPSNN_E_INVAL, "at most 2^36 - 1 synapses per network");
+    // kernels address one column's forward block and reverse rows with 32-bit
+    // offsets: a column's block and the synapses that can reach it (from 13
+    // columns) stay below 2^31
+    if ((uint64_t)kSlots * Ncol * c->synapses_per_neuron >= (1ull << 31))
+        return fail(DPSNN_E_INVAL, "13 x neurons_per_column x synapses_per_neuron must stay below 2^31");
+    if (c->sum_mode == DPSNN_SUM_ORDERED && S >= (1ull << 32))
+        return fail(DPSNN_E_INVAL, "ORDERED summation takes at most 2^32 - 1 synapses");
     if (!finite_in(c->w_exc_init, -1000.f, 1000.f) || !finite_in(c->w_inh, -1000.f, 1000.f) ||
         !finite_in(c->w_max, 0.f, 1000.f))
         return fail(DPSNN_E_INVAL, "weights must be finite, |w| <= 1000, w_max >= 0");
@@ -107,11 +114,11 @@ std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
     std::vector<size_t> b = {
         sizeof(uint32_t) * d.C * kSlots,                  // colmap
         sizeof(uint32_t) * d.C * kSlots,                  // srcmap
-        sizeof(uint32_t) * ((size_t)d.C * d.Dmax * d.Ncol + 1),  // seg_off
+        sizeof(uint64_t) * ((size_t)d.C * d.Dmax * d.Ncol + 1),  // seg_off
         (d.tgt16 ? 2 : 4) * S,                            // tgt
         sizeof(float) * S,                                // w
         sizeof(float) * S,                                // D
-        sizeof(uint32_t) * (N + 1),                       // rowptr
+        sizeof(uint64_t) * (N + 1),                       // rowptr
         sizeof(uint32_t) * N,                             // cursor
         sizeof(uint32_t) * Se,                            // rev_srcd
         sizeof(uint32_t) * Se,                            // rev_fwd
@@ -121,7 +128,7 @@ std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
         sizeof(uint2) * N, sizeof(int32_t) * N,           // hist (with t_old), t_last
         sizeof(uint64_t) * (size_t)d.R * d.C * d.W,       // ring
         sizeof(DevStats) * 64,                            // stats
-        sizeof(uint32_t) * (N / 1024 + 2),                // scan_tmp
+        sizeof(uint64_t) * (N / 1024 + 2),                // scan_tmp
     };
     if (c->sum_mode == DPSNN_SUM_ORDERED) {
         b.push_back(sizeof(uint32_t) * N);                // ev_cnt
@@ -297,9 +304,14 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
         L.min_col_syn = std::min<uint64_t>(L.min_col_syn, (uint64_t)d.Ncol * d.M);
         for (uint32_t c = 0; c < d.C; ++c) col.push_back(make_uint2(k, c));
         for (uint32_t w0 = 0; w0 < d.C * d.W; w0 += 4) neu.push_back(make_uint2(k, w0));
-        const uint64_t nch = (m[k]->S_exc + wchunk - 1) / wchunk;
-        if (nch > 0xFFFFFFFFull) return fail(DPSNN_E_INVAL, "too many consolidation chunks");
-        for (uint64_t q = 0; q < nch; ++q) wu[k].push_back(make_uint2(0u, (uint32_t)q));
+        // consolidation: (target column, chunk of its reverse rows)
+        const std::vector<uint64_t>& cr = m[k]->col_rev;
+        if (cr.size() != (size_t)d.C + 1) return fail(DPSNN_E_INVAL, "network has no reverse index");
+        for (uint32_t c = 0; c < d.C; ++c) {
+            const uint64_t nch = (cr[c + 1] - cr[c] + wchunk - 1) / wchunk;
+            for (uint64_t q = 0; q < nch; ++q) wu[k].push_back(make_uint2(c, (uint32_t)q));
+        }
+        if (wu[k].size() > 0x7FFFFFFFull) return fail(DPSNN_E_INVAL, "too many consolidation chunks");
     }
     // heaviest columns first (synapses per column), so that the longest
     // workgroups start early; stable, so a single network keeps its order
@@ -621,13 +633,13 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
         }
     }
     size_t k = 0;
-    n->colmap = (uint32_t*)p[k++]; n->srcmap = (uint32_t*)p[k++]; n->seg_off = (uint32_t*)p[k++];
+    n->colmap = (uint32_t*)p[k++]; n->srcmap = (uint32_t*)p[k++]; n->seg_off = (uint64_t*)p[k++];
     n->tgt = p[k++]; n->w = (float*)p[k++]; n->Dacc = (float*)p[k++];
-    n->rowptr = (uint32_t*)p[k++]; n->cursor = (uint32_t*)p[k++];
+    n->rowptr = (uint64_t*)p[k++]; n->cursor = (uint32_t*)p[k++];
     n->rev_srcd = (uint32_t*)p[k++]; n->rev_fwd = (uint32_t*)p[k++]; n->Pacc = (float*)p[k++];
     n->v = (float*)p[k++]; n->u = (float*)p[k++]; n->acc = p[k++];
     n->hist = (uint2*)p[k++]; n->t_last = (int32_t*)p[k++];
-    n->ring = (uint64_t*)p[k++]; n->stats = (DevStats*)p[k++]; n->scan_tmp = (uint32_t*)p[k++];
+    n->ring = (uint64_t*)p[k++]; n->stats = (DevStats*)p[k++]; n->scan_tmp = (uint64_t*)p[k++];
     if (cfg->sum_mode == DPSNN_SUM_ORDERED) {
         n->ev_cnt = (uint32_t*)p[k++]; n->ev_start = (uint32_t*)p[k++];
         n->ev_key = (unsigned long long*)p[k++]; n->ev_w = (float*)p[k++];
@@ -688,12 +700,15 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
         DPSNN_TRY_HIP(hipMemsetAsync(n->ev_start, 0, sizeof(uint32_t) * (dv.N + 1), n->stream));
     }
     DPSNN_TRY_HIP(launch_build(*n));
-    // the reverse index must hold exactly the excitatory synapses
-    uint32_t total = 0;
-    DPSNN_TRY_HIP(hipMemcpyAsync(&total, n->rowptr + dv.N, sizeof(uint32_t), hipMemcpyDeviceToHost, n->stream));
+    // where each target column's reverse rows start (consolidation's work
+    // map); the reverse index must hold exactly the excitatory synapses
     DPSNN_TRY_HIP(hipMemsetAsync(n->cursor, 0, sizeof(uint32_t) * dv.N, n->stream));
     DPSNN_TRY_HIP(hipStreamSynchronize(n->stream));
-    if ((uint64_t)total != dv.S_exc) {
+    n->col_rev.assign((size_t)dv.C + 1, 0);
+    DPSNN_TRY_HIP(hipMemcpy2D(n->col_rev.data(), sizeof(uint64_t), n->rowptr,
+                              sizeof(uint64_t) * dv.Ncol, sizeof(uint64_t), (size_t)dv.C + 1,
+                              hipMemcpyDeviceToHost));
+    if (n->col_rev[dv.C] != dv.S_exc) {
         release(n);
         return fail(DPSNN_E_DEVICE, "reverse index size mismatch after build");
     }

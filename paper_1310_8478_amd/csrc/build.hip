@@ -27,7 +27,7 @@ __device__ __forceinline__ unsigned long long same_delay(unsigned long long act,
 }
 
 __global__ __launch_bounds__(256) void k_count_rows(Dims d, const uint32_t* __restrict__ colmap,
-                                                    uint32_t* __restrict__ seg_off,
+                                                    uint64_t* __restrict__ seg_off,
                                                     uint32_t* __restrict__ indeg) {
     const uint32_t row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= d.N) return;  // uniform per wavefront
@@ -54,28 +54,30 @@ __global__ __launch_bounds__(256) void k_count_rows(Dims d, const uint32_t* __re
 }
 
 // Per column: exclusive prefix over its (delay, neuron) segment lengths plus
-// the column's base position.
-__global__ __launch_bounds__(1024) void k_col_scan(Dims d, uint32_t* __restrict__ seg_off) {
+// the column's base position c * Ncol * M (64-bit; a column's own offsets fit
+// 32 bits).
+__global__ __launch_bounds__(1024) void k_col_scan(Dims d, uint64_t* __restrict__ seg_off) {
     __shared__ uint32_t sh[20];
     const uint32_t c = blockIdx.x;
-    uint32_t* p = seg_off + (size_t)c * d.segs;
-    uint32_t carry = c * d.Ncol * d.M;
+    uint64_t* p = seg_off + (size_t)c * d.segs;
+    const uint64_t base = (uint64_t)c * d.Ncol * d.M;
+    uint32_t carry = 0;
     for (uint32_t b0 = 0; b0 < d.segs; b0 += blockDim.x) {
         const uint32_t idx = b0 + threadIdx.x;
-        const uint32_t v = idx < d.segs ? p[idx] : 0u;
+        const uint32_t v = idx < d.segs ? (uint32_t)p[idx] : 0u;
         uint32_t tot;
         const uint32_t ex = block_scan(v, sh, tot);
-        if (idx < d.segs) p[idx] = carry + ex;
+        if (idx < d.segs) p[idx] = base + carry + ex;
         carry += tot;
     }
-    if (c == d.C - 1 && threadIdx.x == 0) seg_off[(size_t)d.C * d.segs] = d.N * d.M;
+    if (c == d.C - 1 && threadIdx.x == 0) seg_off[(size_t)d.C * d.segs] = (uint64_t)d.N * d.M;
 }
 
 template <typename TgtT>
 __global__ __launch_bounds__(256) void k_fill_rows(Dims d, const uint32_t* __restrict__ colmap,
-                                                   const uint32_t* __restrict__ seg_off,
+                                                   const uint64_t* __restrict__ seg_off,
                                                    TgtT* __restrict__ tgt, float* __restrict__ w,
-                                                   const uint32_t* __restrict__ rowptr,
+                                                   const uint64_t* __restrict__ rowptr,
                                                    uint32_t* __restrict__ cursor,
                                                    uint32_t* __restrict__ rev_srcd,
                                                    uint32_t* __restrict__ rev_fwd) {
@@ -84,6 +86,7 @@ __global__ __launch_bounds__(256) void k_fill_rows(Dims d, const uint32_t* __res
     const uint32_t lane = lane_id();
     const uint32_t c = row / d.Ncol;
     const uint32_t l = row - c * d.Ncol;
+    const uint64_t cbase = (uint64_t)c * d.Ncol * d.M;
     uint32_t placed = 0;  // lane L: synapses of delay L + 1 already placed
     for (uint32_t base = 0; base < d.M; base += 64) {
         const uint32_t j = base + lane;
@@ -98,15 +101,15 @@ __global__ __launch_bounds__(256) void k_fill_rows(Dims d, const uint32_t* __res
         const uint32_t rank = (uint32_t)__popcll(mine & lanemask_lt());
         const uint32_t before = __shfl(placed, (int)(s.delay - 1u), 64);
         if (valid) {
-            const uint32_t pos =
+            const uint64_t pos =
                 seg_off[(size_t)c * d.segs + (s.delay - 1u) * d.Ncol + l] + before + rank;
             tgt[pos] = (TgtT)(s.slot * d.Ncol + s.lt);
             w[pos] = s.exc ? d.w_exc : d.w_inh;
             if (s.exc) {
                 const uint32_t kg = colmap[c * kSlots + s.slot] * d.Ncol + s.lt;
-                const uint32_t x = rowptr[kg] + atomicAdd(&cursor[kg], 1u);
+                const uint64_t x = rowptr[kg] + atomicAdd(&cursor[kg], 1u);
                 rev_srcd[x] = (s.slot << 22) | (l << 6) | s.delay;
-                rev_fwd[x] = pos;
+                rev_fwd[x] = (uint32_t)(pos - cbase);
             }
         }
         placed += (uint32_t)__popcll(same_delay(act, bb, lane + 1));
@@ -127,10 +130,13 @@ __global__ void k_init_state(Dims d, float* __restrict__ v, float* __restrict__ 
     t_last[k] = kNoSpike;
 }
 
-// Device-wide exclusive scan: tiles of blockDim elements.
+// Device-wide exclusive scan of 32-bit values into OutT (32- or 64-bit):
+// tiles of blockDim elements (a tile's sum must fit 32 bits), then the tile
+// offsets in OutT.
+template <typename OutT>
 __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict__ in,
-                                                     uint32_t* __restrict__ out,
-                                                     uint32_t* __restrict__ sums, uint32_t n) {
+                                                     OutT* __restrict__ out,
+                                                     OutT* __restrict__ sums, uint32_t n) {
     __shared__ uint32_t sh[20];
     const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t v = idx < n ? in[idx] : 0u;
@@ -140,40 +146,83 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_sums(uint32_t* __restrict__ sums, uint32_t nb,
-                                                    uint32_t* __restrict__ out, uint32_t n) {
-    __shared__ uint32_t sh[20];
-    uint32_t carry = 0;
-    for (uint32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
-        const uint32_t idx = b0 + threadIdx.x;
-        const uint32_t v = idx < nb ? sums[idx] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_scan(v, sh, tot);
-        if (idx < nb) sums[idx] = carry + ex;
-        carry += tot;
+// Exclusive block scan of 64-bit values (same scheme as block_scan).
+__device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t* sh, uint64_t& total) {
+    const uint32_t lane = lane_id();
+    const uint32_t wid = threadIdx.x >> 6;
+    const uint32_t nw = blockDim.x >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
     }
-    if (threadIdx.x == 0) out[n] = carry;
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        const uint64_t s = lane < nw ? sh[lane] : 0ull;
+        uint64_t inc = s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint64_t y = __shfl_up(inc, o, 64);
+            if (lane >= (uint32_t)o) inc += y;
+        }
+        if (lane < nw) sh[lane] = inc - s;
+        if (lane == nw - 1) sh[nw] = inc;
+    }
+    __syncthreads();
+    const uint64_t res = sh[wid] + x - v;
+    total = sh[nw];
+    __syncthreads();
+    return res;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_add(uint32_t* __restrict__ out,
-                                                   const uint32_t* __restrict__ sums, uint32_t n) {
+template <typename OutT>
+__global__ __launch_bounds__(1024) void k_scan_sums(OutT* __restrict__ sums, uint32_t nb,
+                                                    OutT* __restrict__ out, uint32_t n) {
+    __shared__ uint64_t sh[20];
+    uint64_t carry = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
+        const uint32_t idx = b0 + threadIdx.x;
+        const uint64_t v = idx < nb ? (uint64_t)sums[idx] : 0ull;
+        uint64_t tot;
+        const uint64_t ex = block_scan_u64(v, sh, tot);
+        if (idx < nb) sums[idx] = (OutT)(carry + ex);
+        carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = (OutT)carry;
+}
+
+template <typename OutT>
+__global__ __launch_bounds__(1024) void k_scan_add(OutT* __restrict__ out,
+                                                   const OutT* __restrict__ sums, uint32_t n) {
     const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < n) out[idx] += sums[blockIdx.x];
+}
+
+template <typename OutT>
+hipError_t scan_into(Net& n, hipStream_t stream, const uint32_t* in, OutT* out, uint32_t count) {
+    const uint32_t bs = 1024;
+    const uint32_t nb = (count + bs - 1) / bs;
+    if (nb == 0) {
+        return hipMemsetAsync(out, 0, sizeof(OutT), stream);
+    }
+    OutT* sums = (OutT*)n.scan_tmp;
+    hipLaunchKernelGGL(k_scan_tiles<OutT>, dim3(nb), dim3(bs), 0, stream, in, out, sums, count);
+    hipLaunchKernelGGL(k_scan_sums<OutT>, dim3(1), dim3(bs), 0, stream, sums, nb, out, count);
+    hipLaunchKernelGGL(k_scan_add<OutT>, dim3(nb), dim3(bs), 0, stream, out, sums, count);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 // out[0..count) = exclusive prefix of in, out[count] = total, on `stream`.
 hipError_t scan_u32(Net& n, hipStream_t stream, const uint32_t* in, uint32_t* out, uint32_t count) {
-    const uint32_t bs = 1024;
-    const uint32_t nb = (count + bs - 1) / bs;
-    if (nb == 0) {
-        return hipMemsetAsync(out, 0, sizeof(uint32_t), stream);
-    }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(bs), 0, stream, in, out, n.scan_tmp, count);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(bs), 0, stream, n.scan_tmp, nb, out, count);
-    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(bs), 0, stream, out, n.scan_tmp, count);
-    return hipGetLastError();
+    return scan_into<uint32_t>(n, stream, in, out, count);
+}
+
+hipError_t scan_u32_u64(Net& n, hipStream_t stream, const uint32_t* in, uint64_t* out, uint32_t count) {
+    return scan_into<uint64_t>(n, stream, in, out, count);
 }
 
 hipError_t launch_build(Net& n) {
@@ -185,7 +234,7 @@ hipError_t launch_build(Net& n) {
     hipLaunchKernelGGL(k_count_rows, dim3(gb), dim3(256), 0, n.stream, d, n.colmap, n.seg_off,
                        n.cursor);
     hipLaunchKernelGGL(k_col_scan, dim3(d.C), dim3(1024), 0, n.stream, d, n.seg_off);
-    if ((e = scan_u32(n, n.stream, n.cursor, n.rowptr, d.N)) != hipSuccess) return e;
+    if ((e = scan_u32_u64(n, n.stream, n.cursor, n.rowptr, d.N)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(n.cursor, 0, sizeof(uint32_t) * d.N, n.stream)) != hipSuccess) return e;
     // every entry is written below; zeroing keeps stray reads in bounds if not
     if ((e = hipMemsetAsync(n.tgt, 0, (n.tgt16 ? 2 : 4) * (size_t)n.S, n.stream)) != hipSuccess) return e;

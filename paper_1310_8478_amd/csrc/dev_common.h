@@ -47,13 +47,13 @@ struct NetDesc {
     uint32_t t0;                     // steps completed when the launch set was made
     const uint32_t* colmap;          // [C*13]
     const uint32_t* srcmap;          // [C*13]
-    const uint32_t* seg_off;         // [C*segs + 1]
+    const uint64_t* seg_off;         // [C*segs + 1] forward positions
     const void* tgt;                 // uint16_t or uint32_t [S]
     const float* w;                  // [S]
     float* Dacc;                     // [S]
-    const uint32_t* rowptr;          // [N+1]
+    const uint64_t* rowptr;          // [N+1] reverse positions
     const uint32_t* rev_srcd;        // [S_exc]
-    const uint32_t* rev_fwd;         // [S_exc]
+    const uint32_t* rev_fwd;         // [S_exc] forward position - c*Ncol*M of the source column c
     float* Pacc;                     // [S_exc]
     float* v;
     float* u;

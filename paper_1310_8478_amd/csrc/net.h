@@ -88,11 +88,16 @@ struct LaunchSet {
 //   local neuron l with delay d in ascending j, segments ordered by d then l,
 //   so all sources of a column that share a delay are contiguous.
 //     seg_off[c*segs + (d-1)*Ncol + l] = first position of segment (d, l),
-//     seg_off[C*segs] = N*M (so the end of a segment is the next entry).
+//     seg_off[C*segs] = N*M (so the end of a segment is the next entry);
+//     positions are 64-bit, offsets inside one column's block fit 32 bits.
+//     Kernels address a column through pointers offset by its block start
+//     rounded down to a multiple of 4, so 32-bit offsets keep the 16-byte
+//     alignment of the synapse quads.
 //     tgt[pos] = slot*Ncol + local target (window index); w[pos]; D[pos].
 //   reverse index of excitatory synapses, rows by global target id:
-//     rowptr[k] .. rowptr[k+1]; rev_srcd = slot<<22 | local source<<6 | delay;
-//     rev_fwd = forward position; P = potentiation accumulator.
+//     rowptr[k] .. rowptr[k+1] (64-bit); rev_srcd = slot<<22 | local source<<6
+//     | delay; rev_fwd = forward position minus the source column's block
+//     start (32-bit); P = potentiation accumulator.
 //   raster ring: R slots of C*W 64-bit words; stamp s lives in slot s % R.
 struct Net {
     dpsnn_config cfg;
@@ -111,11 +116,11 @@ struct Net {
 
     uint32_t* colmap = nullptr;   // [C*13] column reached from c through slot q
     uint32_t* srcmap = nullptr;   // [C*13] column that reaches c through slot q
-    uint32_t* seg_off = nullptr;  // [C*segs + 1]
+    uint64_t* seg_off = nullptr;  // [C*segs + 1]
     void* tgt = nullptr;          // uint16_t or uint32_t [S]
     float* w = nullptr;           // [S]
     float* Dacc = nullptr;        // [S]
-    uint32_t* rowptr = nullptr;   // [N+1]
+    uint64_t* rowptr = nullptr;   // [N+1]
     uint32_t* cursor = nullptr;   // [N] build scratch; ORDERED event cursor afterwards
     uint32_t* rev_srcd = nullptr; // [S_exc]
     uint32_t* rev_fwd = nullptr;  // [S_exc]
@@ -132,7 +137,7 @@ struct Net {
     float* tm = nullptr;          // [tm_len] LTD amplitudes by dt
     uint32_t tp_len = 0, tm_len = 0;
     DevStats* stats = nullptr;    // [64] spread counters
-    uint32_t* scan_tmp = nullptr; // block sums of the device-wide scan
+    uint64_t* scan_tmp = nullptr; // block sums of the device-wide scans
     // ORDERED mode event buffers
     uint32_t* ev_cnt = nullptr;   // [N]
     uint32_t* ev_start = nullptr; // [N+1]
@@ -155,6 +160,7 @@ struct Net {
     LaunchSet solo;               // this network alone
     bool desc_dirty = true;
     double per_col = 0.0;         // last regime estimate of a set holding this network
+    std::vector<uint64_t> col_rev;  // [C+1] reverse positions where each target column starts
 
     NetDesc make_desc() const;
 };
@@ -185,5 +191,6 @@ hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, float* Pf, uint32_
                             uint8_t* dly_out, float* w_out, float* P_out, float* D_out);
 hipError_t launch_scatter_P(Net& n, float* Pf);
 hipError_t scan_u32(Net& n, hipStream_t stream, const uint32_t* in, uint32_t* out, uint32_t count);
+hipError_t scan_u32_u64(Net& n, hipStream_t stream, const uint32_t* in, uint64_t* out, uint32_t count);
 
 }  // namespace dpsnn

@@ -18,7 +18,7 @@ __device__ __forceinline__ unsigned long long same_delay_r(unsigned long long ac
 
 template <typename TgtT>
 __global__ __launch_bounds__(256) void k_read_rows(Dims d, const uint32_t* __restrict__ colmap,
-                                                   const uint32_t* __restrict__ seg_off,
+                                                   const uint64_t* __restrict__ seg_off,
                                                    const TgtT* __restrict__ tgt,
                                                    const float* __restrict__ w,
                                                    const float* __restrict__ Dacc,
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void k_read_rows(Dims d, const uint32_t* __res
         const uint32_t rank = (uint32_t)__popcll(mine & lanemask_lt());
         const uint32_t before = __shfl(placed, (int)(s.delay - 1u), 64);
         if (valid) {
-            const uint32_t pos =
+            const uint64_t pos =
                 seg_off[(size_t)c * d.segs + (s.delay - 1u) * d.Ncol + l] + before + rank;
             const size_t o = (size_t)(row - i0) * d.M + j;
             const uint32_t wi = (uint32_t)tgt[pos];
@@ -61,12 +61,22 @@ __global__ __launch_bounds__(256) void k_read_rows(Dims d, const uint32_t* __res
     }
 }
 
-__global__ __launch_bounds__(256) void k_scatter_P(uint64_t n, const uint32_t* __restrict__ rev_fwd,
+// P from reverse to forward order.  Workgroups (target column ct, slice y):
+// an entry's source column is the column that reaches ct through the entry's
+// slot, and its forward position is that column's block start plus rev_fwd.
+__global__ __launch_bounds__(256) void k_scatter_P(Dims d, const uint32_t* __restrict__ srcmap,
+                                                   const uint64_t* __restrict__ rowptr,
+                                                   const uint32_t* __restrict__ rev_srcd,
+                                                   const uint32_t* __restrict__ rev_fwd,
                                                    const float* __restrict__ P,
                                                    float* __restrict__ Pf) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride)
-        Pf[rev_fwd[x]] = P[x];
+    const uint32_t ct = blockIdx.x;
+    const uint64_t x0 = rowptr[(size_t)ct * d.Ncol], x1 = rowptr[(size_t)(ct + 1) * d.Ncol];
+    const uint64_t stride = (uint64_t)gridDim.y * blockDim.x;
+    for (uint64_t x = x0 + (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; x < x1; x += stride) {
+        const uint32_t src = srcmap[ct * kSlots + (rev_srcd[x] >> 22)];
+        Pf[(uint64_t)src * d.Ncol * d.M + rev_fwd[x]] = P[x];
+    }
 }
 
 }  // namespace
@@ -75,9 +85,8 @@ hipError_t launch_scatter_P(Net& n, float* Pf) {
     hipError_t e = hipMemsetAsync(Pf, 0, sizeof(float) * n.S, n.stream);
     if (e != hipSuccess) return e;
     if (n.S_exc == 0) return hipSuccess;
-    const uint64_t blocks = std::min<uint64_t>((n.S_exc + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_scatter_P, dim3((uint32_t)blocks), dim3(256), 0, n.stream, n.S_exc,
-                       n.rev_fwd, n.Pacc, Pf);
+    hipLaunchKernelGGL(k_scatter_P, dim3(n.d.C, 16), dim3(256), 0, n.stream, n.d, n.srcmap,
+                       n.rowptr, n.rev_srcd, n.rev_fwd, n.Pacc, Pf);
     return hipGetLastError();
 }
 

@@ -43,10 +43,14 @@ __device__ __forceinline__ void ltp_body(const NetDesc* __restrict__ nds,
     if (t < 1) return;  // no stamp 0: nothing to potentiate in the first step
     const uint64_t* __restrict__ ring = nd.ring;
     const uint2* __restrict__ hist = nd.hist;
-    const uint32_t* __restrict__ rowptr = nd.rowptr;
-    const uint32_t* __restrict__ rev_srcd = nd.rev_srcd;
-    float* __restrict__ P = nd.Pacc;
+    const uint64_t* __restrict__ rowptr = nd.rowptr;
     const uint32_t* __restrict__ srcmap = nd.srcmap;
+    // the target column's reverse rows through pointers offset by their start
+    // rounded down to a multiple of 4: 32-bit offsets, aligned quads
+    const uint32_t ct = br.y;
+    const uint64_t rb = rowptr[(size_t)ct * d.Ncol] & ~3ull;
+    const uint32_t* __restrict__ rev_srcd = nd.rev_srcd + rb;
+    float* __restrict__ P = nd.Pacc + rb;
     const float* __restrict__ tp = nd.tp;
     const uint32_t tp_len = nd.tp_len;
     DevStats* __restrict__ stats = nd.stats;
@@ -59,7 +63,6 @@ __device__ __forceinline__ void ltp_body(const NetDesc* __restrict__ nds,
     float* tph = (float*)(smap + 16);  // [64] first LTP amplitudes
     uint32_t* hwin = smap + 16 + 64;   // [13 * Ncol] when staged
     const uint32_t tid = threadIdx.x;
-    const uint32_t ct = br.y;
     const uint64_t* words = ring + ((size_t)(t % d.R) * d.C + ct) * d.W;
 
     // the column's raster words and the small tables, loaded together
@@ -96,8 +99,8 @@ __device__ __forceinline__ void ltp_body(const NetDesc* __restrict__ nds,
     if (nsp == d.Ncol) {
         // every neuron of the column fired: its reverse rows form one block
         __syncthreads();
-        const uint32_t c_lo = rowptr[ct * d.Ncol];
-        const uint32_t c_hi = rowptr[(ct + 1) * d.Ncol];
+        const uint32_t c_lo = (uint32_t)(rowptr[(size_t)ct * d.Ncol] - rb);
+        const uint32_t c_hi = (uint32_t)(rowptr[(size_t)(ct + 1) * d.Ncol] - rb);
         const uint32_t x_lo = part_bound4(c_lo, c_hi, part, nparts);
         const uint32_t x_hi = part_bound4(c_lo, c_hi, part + 1u, nparts);
         const uint32_t total = x_hi - x_lo;
@@ -197,8 +200,9 @@ __device__ __forceinline__ void ltp_body(const NetDesc* __restrict__ nds,
         if (tid < nr) {
             const uint32_t le = min(pref[tid], d.Ncol);
             const uint32_t ls = min(x0[tid], le);
-            a = rowptr[ct * d.Ncol + ls];
-            len = rowptr[ct * d.Ncol + le] - a;
+            const uint64_t ga = rowptr[(size_t)ct * d.Ncol + ls];
+            a = (uint32_t)(ga - rb);
+            len = (uint32_t)(rowptr[(size_t)ct * d.Ncol + le] - ga);
         }
         __syncthreads();
         uint32_t E;
@@ -291,10 +295,13 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     const uint32_t t = nd.t0 + tstep;
     if (t < 1) return;  // no spike has been stamped yet
     const uint64_t* __restrict__ ring = nd.ring;
-    const uint32_t* __restrict__ seg_off = nd.seg_off;
-    const TgtT* __restrict__ tgt = (const TgtT*)nd.tgt;
-    const float* __restrict__ w = nd.w;
-    float* __restrict__ Dacc = nd.Dacc;
+    const uint64_t* __restrict__ seg_off = nd.seg_off;
+    // the source column's forward block through pointers offset by its start
+    // rounded down to a multiple of 4: 32-bit offsets, aligned quads
+    const uint64_t fb = ((uint64_t)br.y * d.Ncol * d.M) & ~3ull;
+    const TgtT* __restrict__ tgt = (const TgtT*)nd.tgt + fb;
+    const float* __restrict__ w = nd.w + fb;
+    float* __restrict__ Dacc = nd.Dacc + fb;
     const int32_t* __restrict__ t_last = nd.t_last;
     const uint32_t* __restrict__ colmap = nd.colmap;
     const float* __restrict__ tm = nd.tm;
@@ -355,8 +362,8 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     bool staged = false;
     // the column's inhibitory synapses (all of delay 1) form one forward range
     const size_t s1 = (size_t)c * d.segs;
-    const uint32_t inh_lo = d.Ne < d.Ncol ? seg_off[s1 + d.Ne] : 0u;
-    const uint32_t inh_hi = d.Ne < d.Ncol ? seg_off[s1 + d.Ncol] : 0u;
+    const uint32_t inh_lo = d.Ne < d.Ncol ? (uint32_t)(seg_off[s1 + d.Ne] - fb) : 0u;
+    const uint32_t inh_hi = d.Ne < d.Ncol ? (uint32_t)(seg_off[s1 + d.Ncol] - fb) : 0u;
     auto is_exc = [&](uint32_t p) { return !(p >= inh_lo && p < inh_hi); };
     auto global_id = [&](uint32_t wi) {
         const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, wi) : wi / d.Ncol;
@@ -410,7 +417,7 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     __syncthreads();
     full = __syncthreads_and(full);
     if (full) {
-        const uint32_t c0 = c * d.Ncol * d.M;
+        const uint32_t c0 = (uint32_t)((uint64_t)c * d.Ncol * d.M - fb);
         const uint32_t cb = part_bound4(c0, c0 + d.Ncol * d.M, part, nparts);
         const uint32_t total = part_bound4(c0, c0 + d.Ncol * d.M, part + 1u, nparts) - cb;
         if (allow_age && total >= nwin) {  // block-uniform
@@ -543,8 +550,8 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
                     const uint32_t ls = min(pos0[tid], le);
                     const uint32_t rd = min(max(excf[tid], 1u), d.Dmax);
                     const size_t sb = (size_t)c * d.segs + (size_t)(rd - 1u) * d.Ncol;
-                    a = seg_off[sb + ls];
-                    e = max(a, seg_off[sb + le]);
+                    a = (uint32_t)(seg_off[sb + ls] - fb);
+                    e = max(a, (uint32_t)(seg_off[sb + le] - fb));
                     nq = e > a ? ((e + 3u) >> 2) - (a >> 2) : 0u;
                 }
                 __syncthreads();
@@ -706,7 +713,7 @@ __global__ __launch_bounds__(256) void k_deliver_seq(const NetDesc* __restrict__
     const uint32_t t = nd.t0 + tstep;
     if (t < 1) return;
     const uint64_t* __restrict__ ring = nd.ring;
-    const uint32_t* __restrict__ seg_off = nd.seg_off;
+    const uint64_t* __restrict__ seg_off = nd.seg_off;  // below 2^32 in this mode
     const TgtT* __restrict__ tgt = (const TgtT*)nd.tgt;
     const float* __restrict__ w = nd.w;
     float* __restrict__ Dacc = nd.Dacc;
@@ -738,7 +745,7 @@ __global__ __launch_bounds__(256) void k_deliver_seq(const NetDesc* __restrict__
             const uint32_t i = c * d.Ncol + l;
             const bool exc = l < d.Ne;
             const size_t sg = (size_t)c * d.segs + (size_t)(dd - 1u) * d.Ncol + l;
-            const uint32_t p0 = seg_off[sg], p1 = seg_off[sg + 1];
+            const uint32_t p0 = (uint32_t)seg_off[sg], p1 = (uint32_t)seg_off[sg + 1];
             for (uint32_t pos = p0 + lane; pos < p1; pos += 64) {
                 const uint32_t wi = (uint32_t)tgt[pos];
                 const uint32_t sl = wi / d.Ncol;
@@ -937,19 +944,29 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
 //   k_wupdate_fwd (forward order, coalesced): w <- clamp(w + (bias + D)); D <- 0
 // for the excitatory positions (the inhibitory synapses of a column are one
 // delay-1 range of its forward block, which the second pass skips).
+// Workgroup (target column ct, chunk q) of the map: entries of ct's reverse
+// rows; an entry's forward position is the block start of the column that
+// reaches ct through its slot plus rev_fwd.
 __global__ __launch_bounds__(256) void k_wupdate(const NetDesc* __restrict__ nds,
                                                  const uint2* __restrict__ bmap) {
+    __shared__ uint32_t smap[kSlots];
     const uint2 br = bmap[blockIdx.x];
-    const NetDesc& nd = nds[br.x];
+    const NetDesc& nd = *nds;
+    const Dims d = nd.d;
+    const uint32_t* __restrict__ rev_srcd = nd.rev_srcd;
     const uint32_t* __restrict__ rev_fwd = nd.rev_fwd;
     float* __restrict__ P = nd.Pacc;
     float* __restrict__ Dacc = nd.Dacc;
     const float decay = nd.sd_decay;
-    const unsigned long long chunk = (unsigned long long)blockDim.x * kWupdateItems;
-    const unsigned long long x0 = (unsigned long long)br.y * chunk;
-    const unsigned long long x1 = min(x0 + chunk, nd.S_exc);
-    for (unsigned long long x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
-        const uint32_t f = rev_fwd[x];
+    const uint32_t ct = br.x;
+    if (threadIdx.x < kSlots) smap[threadIdx.x] = nd.srcmap[ct * kSlots + threadIdx.x];
+    __syncthreads();
+    const uint64_t colsz = (uint64_t)d.Ncol * d.M;
+    const uint64_t chunk = (uint64_t)blockDim.x * kWupdateItems;
+    const uint64_t x0 = nd.rowptr[(size_t)ct * d.Ncol] + (uint64_t)br.y * chunk;
+    const uint64_t x1 = min(x0 + chunk, nd.rowptr[(size_t)(ct + 1) * d.Ncol]);
+    for (uint64_t x = x0 + threadIdx.x; x < x1; x += blockDim.x) {
+        const uint64_t f = (uint64_t)smap[rev_srcd[x] >> 22] * colsz + rev_fwd[x];
         const float sd = P[x] - Dacc[f];
         Dacc[f] = sd;
         P[x] = decay * sd;
@@ -965,7 +982,7 @@ __global__ __launch_bounds__(64) void k_rebase(NetDesc* __restrict__ nds, uint32
 __global__ __launch_bounds__(256) void k_wupdate_fwd(const NetDesc* __restrict__ nds) {
     const NetDesc& nd = *nds;
     const Dims d = nd.d;
-    const uint32_t* __restrict__ seg_off = nd.seg_off;
+    const uint64_t* __restrict__ seg_off = nd.seg_off;
     float* __restrict__ Dacc = nd.Dacc;
     float* __restrict__ w = (float*)nd.w;
     const float bias = nd.wu_bias, wmax = nd.w_max;
@@ -974,14 +991,15 @@ __global__ __launch_bounds__(256) void k_wupdate_fwd(const NetDesc* __restrict__
     const uint64_t chunk = (uint64_t)blockDim.x * kWupdateItems;
     const uint64_t f0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t f1 = min(f0 + chunk, S);
-    uint32_t cur = 0xFFFFFFFFu, lo = 0, hi = 0;  // inhibitory range of column cur
+    uint32_t cur = 0xFFFFFFFFu;
+    uint64_t lo = 0, hi = 0;  // inhibitory range of column cur
     for (uint64_t f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
         const uint32_t c = (uint32_t)(f / colsz);
         if (c != cur) {
             cur = c;
             const size_t s1 = (size_t)c * d.segs;
-            lo = d.Ne < d.Ncol ? seg_off[s1 + d.Ne] : 0u;
-            hi = d.Ne < d.Ncol ? seg_off[s1 + d.Ncol] : 0u;
+            lo = d.Ne < d.Ncol ? seg_off[s1 + d.Ne] : 0ull;
+            hi = d.Ne < d.Ncol ? seg_off[s1 + d.Ncol] : 0ull;
         }
         if (f >= lo && f < hi) continue;
         float nw = w[f] + (bias + Dacc[f]);

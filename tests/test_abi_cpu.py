@@ -61,9 +61,22 @@ def test_invalid_configs_rejected(dp, field, value):
 
 
 def test_size_limits(dp):
-    # 2^32 synapses would overflow 32-bit forward positions
+    # 64-bit positions: the paper's largest grid (256x128 columns, 6.55 G
+    # synapses) is valid and fits one 288 GB device
+    big = W.paper_table1(8)
+    fp = dp.footprint_bytes(big)
+    assert 1.2e11 < fp < 1.6e11
+    # ... but not in ORDERED mode (32-bit event slots)
     with pytest.raises(dp.DpsnnError):
-        dp.footprint_bytes(W.make_config(grid_x=128, grid_y=128, synapses_per_neuron=2000))
+        dp.footprint_bytes(dict(big, sum_mode=W.SUM_ORDERED))
+    # 2^36 synapses
+    with pytest.raises(dp.DpsnnError):
+        dp.footprint_bytes(W.make_config(grid_x=256, grid_y=256, neurons_per_column=1000,
+                                         synapses_per_neuron=1100))
+    # one column's reach (13 x Ncol x M) must stay below 2^31
+    with pytest.raises(dp.DpsnnError):
+        dp.footprint_bytes(W.make_config(grid_x=1, grid_y=1, neurons_per_column=65535,
+                                         synapses_per_neuron=2600))
     # 2^26 neurons is the id limit
     with pytest.raises(dp.DpsnnError):
         dp.footprint_bytes(W.make_config(grid_x=256, grid_y=256, neurons_per_column=1100,
