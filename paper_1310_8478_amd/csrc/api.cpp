@@ -129,6 +129,7 @@ std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
         sizeof(uint64_t) * (size_t)d.R * d.C * d.W,       // ring
         sizeof(DevStats) * 64,                            // stats
         sizeof(uint64_t) * (N / 1024 + 2),                // scan_tmp
+        sizeof(uint64_t) * ((size_t)d.C + 1),             // column starts of the reverse rows
     };
     if (c->sum_mode == DPSNN_SUM_ORDERED) {
         b.push_back(sizeof(uint32_t) * N);                // ev_cnt
@@ -640,6 +641,7 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     n->v = (float*)p[k++]; n->u = (float*)p[k++]; n->acc = p[k++];
     n->hist = (uint2*)p[k++]; n->t_last = (int32_t*)p[k++];
     n->ring = (uint64_t*)p[k++]; n->stats = (DevStats*)p[k++]; n->scan_tmp = (uint64_t*)p[k++];
+    n->col_rev_dev = (uint64_t*)p[k++];
     if (cfg->sum_mode == DPSNN_SUM_ORDERED) {
         n->ev_cnt = (uint32_t*)p[k++]; n->ev_start = (uint32_t*)p[k++];
         n->ev_key = (unsigned long long*)p[k++]; n->ev_w = (float*)p[k++];
@@ -702,12 +704,11 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     DPSNN_TRY_HIP(launch_build(*n));
     // where each target column's reverse rows start (consolidation's work
     // map); the reverse index must hold exactly the excitatory synapses
+    n->col_rev.assign((size_t)dv.C + 1, 0);
+    DPSNN_TRY_HIP(hipMemcpyAsync(n->col_rev.data(), n->col_rev_dev, sizeof(uint64_t) * ((size_t)dv.C + 1),
+                                 hipMemcpyDeviceToHost, n->stream));
     DPSNN_TRY_HIP(hipMemsetAsync(n->cursor, 0, sizeof(uint32_t) * dv.N, n->stream));
     DPSNN_TRY_HIP(hipStreamSynchronize(n->stream));
-    n->col_rev.assign((size_t)dv.C + 1, 0);
-    DPSNN_TRY_HIP(hipMemcpy2D(n->col_rev.data(), sizeof(uint64_t), n->rowptr,
-                              sizeof(uint64_t) * dv.Ncol, sizeof(uint64_t), (size_t)dv.C + 1,
-                              hipMemcpyDeviceToHost));
     if (n->col_rev[dv.C] != dv.S_exc) {
         release(n);
         return fail(DPSNN_E_DEVICE, "reverse index size mismatch after build");

@@ -146,6 +146,14 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
+// out[c] = rowptr[c * Ncol] for c = 0 .. C: where each target column's
+// reverse rows start.
+__global__ __launch_bounds__(256) void k_col_starts(Dims d, const uint64_t* __restrict__ rowptr,
+                                                    uint64_t* __restrict__ out) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c <= d.C) out[c] = rowptr[(size_t)c * d.Ncol];
+}
+
 // Exclusive block scan of 64-bit values (same scheme as block_scan).
 __device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t* sh, uint64_t& total) {
     const uint32_t lane = lane_id();
@@ -253,6 +261,8 @@ hipError_t launch_build(Net& n) {
     }
     hipLaunchKernelGGL(k_init_state, dim3((d.N + 255) / 256), dim3(256), 0, n.stream, d, n.v, n.u,
                        n.hist, n.t_last);
+    hipLaunchKernelGGL(k_col_starts, dim3((d.C + 1 + 255) / 256), dim3(256), 0, n.stream, d,
+                       n.rowptr, n.col_rev_dev);
     return hipGetLastError();
 }
 

@@ -138,6 +138,7 @@ struct Net {
     uint32_t tp_len = 0, tm_len = 0;
     DevStats* stats = nullptr;    // [64] spread counters
     uint64_t* scan_tmp = nullptr; // block sums of the device-wide scans
+    uint64_t* col_rev_dev = nullptr;  // [C+1] copy source of col_rev
     // ORDERED mode event buffers
     uint32_t* ev_cnt = nullptr;   // [N]
     uint32_t* ev_start = nullptr; // [N+1]
