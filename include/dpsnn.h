@@ -219,6 +219,29 @@ int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
  * network advances by those steps; its results do not depend on the shapes. */
 int dpsnn_autotune(dpsnn_net *net, uint32_t steps_per_trial);
 
+/* The network's configuration (raster_steps as resolved at build). */
+int dpsnn_get_config(dpsnn_net *net, dpsnn_config *cfg);
+
+/* ---- Checkpoints ------------------------------------------------------
+ * A checkpoint holds the configuration and the dynamic state after the last
+ * completed step: v, u, spike history, latest spike stamps, the raster ring,
+ * w, P, D, the stimulus list, the clock and the counters (the paper warms a
+ * network for 8 s before measuring; a checkpoint skips that).  Connectivity
+ * is not stored: dpsnn_load regenerates it from the seed, exactly as the
+ * build drew it.  A loaded network continues bit for bit as the saved one
+ * would have in the reproducible summation modes.  Launch shapes, timers and
+ * the regime estimate are not stored. */
+
+/* Bytes dpsnn_save writes for this network. */
+int dpsnn_checkpoint_bytes(dpsnn_net *net, uint64_t *bytes);
+/* Write the checkpoint into the caller's host buffer buf of cap bytes
+ * (DPSNN_E_BUFSZ if too small); waits for the network's stream. */
+int dpsnn_save(dpsnn_net *net, void *buf, uint64_t cap);
+/* Build a network on *dev from a checkpoint of `size` bytes (as written by
+ * dpsnn_save) and restore its state; DPSNN_E_INVAL if buf is not a whole,
+ * consistent checkpoint of this format.  *out is owned by the caller. */
+int dpsnn_load(const void *buf, uint64_t size, const dpsnn_device *dev, dpsnn_net **out);
+
 void dpsnn_destroy(dpsnn_net *net);
 
 /* ---- Batches: many independent networks advanced together ----------------

@@ -535,6 +535,55 @@ struct dpsnn_batch {
     std::vector<Net::Alloc> allocs;
 };
 
+// ---- checkpoints -------------------------------------------------------
+// A checkpoint holds the configuration and the dynamic state; the
+// connectivity is regenerated from the seed when it is loaded.  Layout: the
+// header, then the arrays of ckpt_parts in order, each padded to 16 bytes.
+// P is stored in the forward layout: the order of entries inside a reverse
+// row depends on the build's atomics, the forward layout does not.
+namespace {
+
+constexpr char kCkptMagic[8] = {'D', 'P', 'S', 'N', 'N', 'C', 'K', '1'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    dpsnn_config cfg;
+    uint64_t t, consolidations, stim_n, total_bytes;
+};
+
+struct CkptPart {
+    void* dev;
+    size_t bytes;
+};
+
+size_t pad16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+std::vector<CkptPart> ckpt_parts(const Net& n, uint64_t stim_n) {
+    const size_t N = n.d.N;
+    return {{n.v, 4 * N},
+            {n.u, 4 * N},
+            {n.hist, sizeof(uint2) * N},
+            {n.t_last, 4 * N},
+            {n.ring, sizeof(uint64_t) * (size_t)n.d.R * n.d.C * n.d.W},
+            {n.stats, sizeof(DevStats) * 64},
+            {n.w, 4 * (size_t)n.S},
+            {n.Dacc, 4 * (size_t)n.S},
+            {nullptr, 4 * (size_t)n.S},  // P in the forward layout (through a buffer)
+            {n.stim_t, 4 * (size_t)stim_n},
+            {n.stim_id, 4 * (size_t)stim_n},
+            {n.stim_mv, 4 * (size_t)stim_n}};
+}
+
+uint64_t ckpt_total(const std::vector<CkptPart>& parts) {
+    uint64_t tot = pad16(sizeof(CkptHeader));
+    for (const CkptPart& q : parts) tot += pad16(q.bytes);
+    return tot;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* dpsnn_last_error(void) { return g_err.c_str(); }
@@ -990,6 +1039,127 @@ int dpsnn_autotune(dpsnn_net* h, uint32_t steps_per_trial) {
         n->desc_dirty = false;
     }
     return autotune(n->solo, n->tune, n->timers, n->stream, one, steps_per_trial);
+}
+
+int dpsnn_get_config(dpsnn_net* h, dpsnn_config* cfg) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n || !cfg) return fail(DPSNN_E_INVAL, "NULL argument");
+    *cfg = n->cfg;
+    return DPSNN_OK;
+}
+
+int dpsnn_checkpoint_bytes(dpsnn_net* h, uint64_t* bytes) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n || !bytes) return fail(DPSNN_E_INVAL, "NULL argument");
+    *bytes = ckpt_total(ckpt_parts(*n, n->stim_n));
+    return DPSNN_OK;
+}
+
+int dpsnn_save(dpsnn_net* h, void* buf, uint64_t cap) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n || !buf) return fail(DPSNN_E_INVAL, "NULL argument");
+    const std::vector<CkptPart> parts = ckpt_parts(*n, n->stim_n);
+    const uint64_t total = ckpt_total(parts);
+    if (cap < total) return fail(DPSNN_E_BUFSZ, "checkpoint buffer too small");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    DPSNN_HIP(hipStreamSynchronize(n->stream));
+    unsigned char* out = static_cast<unsigned char*>(buf);
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof(hd));
+    std::memcpy(hd.magic, kCkptMagic, sizeof(kCkptMagic));
+    hd.version = kCkptVersion;
+    hd.header_bytes = (uint32_t)sizeof(CkptHeader);
+    hd.cfg = n->cfg;
+    hd.t = n->t;
+    hd.consolidations = n->consolidations;
+    hd.stim_n = n->stim_n;
+    hd.total_bytes = total;
+    std::memset(out, 0, pad16(sizeof(hd)));
+    std::memcpy(out, &hd, sizeof(hd));
+    float* Pf = nullptr;
+    if (hipMalloc((void**)&Pf, sizeof(float) * std::max<uint64_t>(n->S, 1)) != hipSuccess)
+        return fail(DPSNN_E_NOMEM, "temporary P buffer");
+    hipError_t e = launch_scatter_P(*n, Pf);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    size_t off = pad16(sizeof(hd));
+    for (const CkptPart& q : parts) {
+        if (e == hipSuccess && q.bytes)
+            e = hipMemcpy(out + off, q.dev ? q.dev : (void*)Pf, q.bytes, hipMemcpyDeviceToHost);
+        off += pad16(q.bytes);
+    }
+    (void)hipFree(Pf);
+    if (e != hipSuccess) return fail(DPSNN_E_DEVICE, hipGetErrorString(e));
+    return DPSNN_OK;
+}
+
+int dpsnn_load(const void* buf, uint64_t size, const dpsnn_device* dev, dpsnn_net** out) {
+    if (!out) return fail(DPSNN_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!buf || size < sizeof(CkptHeader)) return fail(DPSNN_E_INVAL, "not a checkpoint (too short)");
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, kCkptMagic, sizeof(kCkptMagic)) != 0)
+        return fail(DPSNN_E_INVAL, "not a checkpoint (bad magic)");
+    if (hd.version != kCkptVersion || hd.header_bytes != sizeof(CkptHeader))
+        return fail(DPSNN_E_INVAL, "checkpoint of another format version");
+    Derived dv;
+    int rc = validate(&hd.cfg, &dv);
+    if (rc) return rc;
+    if (hd.cfg.raster_steps != dv.R || hd.t >= (1ull << 31) || hd.stim_n > 0xFFFFFFFFull ||
+        hd.total_bytes != size)
+        return fail(DPSNN_E_INVAL, "inconsistent checkpoint header");
+    dpsnn_net* h = nullptr;
+    rc = dpsnn_build_network(&hd.cfg, dev, &h);
+    if (rc) return rc;
+    Net* n = reinterpret_cast<Net*>(h);
+    const unsigned char* in = static_cast<const unsigned char*>(buf);
+    const size_t stim_off = [&] {
+        size_t o = pad16(sizeof(CkptHeader));
+        const std::vector<CkptPart> p0 = ckpt_parts(*n, hd.stim_n);
+        for (size_t k = 0; k + 3 < p0.size(); ++k) o += pad16(p0[k].bytes);
+        return o;
+    }();
+    if (ckpt_total(ckpt_parts(*n, hd.stim_n)) != size) {
+        release(n);
+        return fail(DPSNN_E_INVAL, "checkpoint size does not match its configuration");
+    }
+    // the stimulus list first (it allocates), then every state array
+    if (hd.stim_n) {
+        const uint32_t* st = reinterpret_cast<const uint32_t*>(in + stim_off);
+        const uint32_t* si = reinterpret_cast<const uint32_t*>(in + stim_off + pad16(4 * hd.stim_n));
+        const float* sm = reinterpret_cast<const float*>(in + stim_off + 2 * pad16(4 * hd.stim_n));
+        rc = dpsnn_set_stimulus(h, st, si, sm, (size_t)hd.stim_n);
+        if (rc) {
+            release(n);
+            return rc;
+        }
+    }
+    const std::vector<CkptPart> parts = ckpt_parts(*n, hd.stim_n);
+    float* Pf = nullptr;
+    if (hipMalloc((void**)&Pf, sizeof(float) * std::max<uint64_t>(n->S, 1)) != hipSuccess) {
+        release(n);
+        return fail(DPSNN_E_NOMEM, "temporary P buffer");
+    }
+    hipError_t e = hipSuccess;
+    size_t off = pad16(sizeof(CkptHeader));
+    for (size_t k = 0; k + 3 < parts.size(); ++k) {
+        const CkptPart& q = parts[k];
+        if (e == hipSuccess && q.bytes)
+            e = hipMemcpy(q.dev ? q.dev : (void*)Pf, in + off, q.bytes, hipMemcpyHostToDevice);
+        off += pad16(q.bytes);
+    }
+    if (e == hipSuccess) e = launch_gather_P(*n, Pf);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    (void)hipFree(Pf);
+    if (e != hipSuccess) {
+        release(n);
+        return fail(DPSNN_E_DEVICE, std::string("checkpoint upload failed: ") + hipGetErrorString(e));
+    }
+    n->t = (uint32_t)hd.t;
+    n->consolidations = hd.consolidations;
+    n->desc_dirty = true;  // descriptors take t0 = t at the next step
+    *out = h;
+    return DPSNN_OK;
 }
 
 void dpsnn_destroy(dpsnn_net* h) {

@@ -190,7 +190,11 @@ hipError_t launch_steps(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_
                         Net* const* members, uint32_t n_steps);
 hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, float* Pf, uint32_t* tgt_out,
                             uint8_t* dly_out, float* w_out, float* P_out, float* D_out);
+// P between the reverse order (whose order inside a row depends on the build's
+// atomics) and the forward layout (fixed by the configuration): Pf has S
+// entries, zero at inhibitory positions.
 hipError_t launch_scatter_P(Net& n, float* Pf);
+hipError_t launch_gather_P(Net& n, const float* Pf);
 hipError_t scan_u32(Net& n, hipStream_t stream, const uint32_t* in, uint32_t* out, uint32_t count);
 hipError_t scan_u32_u64(Net& n, hipStream_t stream, const uint32_t* in, uint64_t* out, uint32_t count);
 

@@ -79,7 +79,30 @@ __global__ __launch_bounds__(256) void k_scatter_P(Dims d, const uint32_t* __res
     }
 }
 
+// The inverse: P[x] = Pf[forward position of x].
+__global__ __launch_bounds__(256) void k_gather_P(Dims d, const uint32_t* __restrict__ srcmap,
+                                                  const uint64_t* __restrict__ rowptr,
+                                                  const uint32_t* __restrict__ rev_srcd,
+                                                  const uint32_t* __restrict__ rev_fwd,
+                                                  const float* __restrict__ Pf,
+                                                  float* __restrict__ P) {
+    const uint32_t ct = blockIdx.x;
+    const uint64_t x0 = rowptr[(size_t)ct * d.Ncol], x1 = rowptr[(size_t)(ct + 1) * d.Ncol];
+    const uint64_t stride = (uint64_t)gridDim.y * blockDim.x;
+    for (uint64_t x = x0 + (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; x < x1; x += stride) {
+        const uint32_t src = srcmap[ct * kSlots + (rev_srcd[x] >> 22)];
+        P[x] = Pf[(uint64_t)src * d.Ncol * d.M + rev_fwd[x]];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_gather_P(Net& n, const float* Pf) {
+    if (n.S_exc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_P, dim3(n.d.C, 16), dim3(256), 0, n.stream, n.d, n.srcmap,
+                       n.rowptr, n.rev_srcd, n.rev_fwd, Pf, n.Pacc);
+    return hipGetLastError();
+}
 
 hipError_t launch_scatter_P(Net& n, float* Pf) {
     hipError_t e = hipMemsetAsync(Pf, 0, sizeof(float) * n.S, n.stream);

@@ -84,6 +84,7 @@ EXPORTS = [
     "dpsnn_sync", "dpsnn_time", "dpsnn_read_spikes", "dpsnn_read_weights",
     "dpsnn_read_connectivity", "dpsnn_read_state", "dpsnn_get_stats", "dpsnn_set_stimulus",
     "dpsnn_set_timing", "dpsnn_set_tuning", "dpsnn_autotune", "dpsnn_destroy",
+    "dpsnn_get_config", "dpsnn_checkpoint_bytes", "dpsnn_save", "dpsnn_load",
     "dpsnn_batch_create", "dpsnn_batch_step", "dpsnn_batch_get_stats", "dpsnn_batch_set_timing",
     "dpsnn_batch_set_tuning", "dpsnn_batch_autotune", "dpsnn_batch_destroy",
     "dpsnn_server_create", "dpsnn_server_submit", "dpsnn_server_query", "dpsnn_server_wait",
@@ -124,6 +125,10 @@ def lib():
         L.dpsnn_autotune.argtypes = [vp, C.c_uint32]
         L.dpsnn_destroy.argtypes = [vp]
         L.dpsnn_destroy.restype = None
+        L.dpsnn_get_config.argtypes = [vp, P(dpsnn_config)]
+        L.dpsnn_checkpoint_bytes.argtypes = [vp, P(C.c_uint64)]
+        L.dpsnn_save.argtypes = [vp, vp, C.c_uint64]
+        L.dpsnn_load.argtypes = [vp, C.c_uint64, P(dpsnn_device), P(vp)]
         L.dpsnn_batch_create.argtypes = [P(vp), C.c_uint32, P(vp)]
         L.dpsnn_batch_step.argtypes = [vp, C.c_uint32]
         L.dpsnn_batch_get_stats.argtypes = [vp, P(dpsnn_stats)]
@@ -206,6 +211,12 @@ class Network:
     def __init__(self, cfg: dict, device: int = 0, stream=None, torch_alloc: bool = True):
         self.cfg = dict(cfg)
         self._c = to_config(cfg)
+        dev = self._device(device, stream, torch_alloc)
+        h = C.c_void_p()
+        _check(lib().dpsnn_build_network(C.byref(self._c), C.byref(dev), C.byref(h)))
+        self._adopt(h)
+
+    def _device(self, device, stream, torch_alloc):
         self._allocator = None
         dev = dpsnn_device()
         dev.device = device
@@ -223,12 +234,45 @@ class Network:
             dev.free = self._allocator.free
         dev.ctx = None
         self._dev = dev
-        h = C.c_void_p()
-        _check(lib().dpsnn_build_network(C.byref(self._c), C.byref(dev), C.byref(h)))
+        return dev
+
+    def _adopt(self, h):
         self.h = h
         self.Ncol = self._c.neurons_per_column
         self.N = self._c.grid_x * self._c.grid_y * self.Ncol
         self.M = self._c.synapses_per_neuron
+
+    def save(self, path=None):
+        """Checkpoint (dpsnn_save) as a uint8 array, also written to `path`
+        if one is given."""
+        n = C.c_uint64()
+        _check(lib().dpsnn_checkpoint_bytes(self.h, C.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(lib().dpsnn_save(self.h, buf.ctypes.data, n.value))
+        if path is not None:
+            buf.tofile(path)
+        return buf
+
+    @classmethod
+    def load(cls, src, device: int = 0, stream=None, torch_alloc: bool = True):
+        """A network restored from a checkpoint (a path or the bytes of one)."""
+        if isinstance(src, (str, os.PathLike)):
+            buf = np.fromfile(src, dtype=np.uint8)
+        else:
+            buf = np.ascontiguousarray(np.frombuffer(src, dtype=np.uint8))
+        self = cls.__new__(cls)
+        dev = self._device(device, stream, torch_alloc)
+        h = C.c_void_p()
+        _check(lib().dpsnn_load(buf.ctypes.data, buf.size, C.byref(dev), C.byref(h)))
+        c = dpsnn_config()
+        rc = lib().dpsnn_get_config(h, C.byref(c))
+        if rc != 0:
+            lib().dpsnn_destroy(h)
+            _check(rc)
+        self._c = c
+        self.cfg = {name: getattr(c, name) for name, _ in dpsnn_config._fields_}
+        self._adopt(h)
+        return self
 
     @classmethod
     def _view(cls, handle: int, cfg: dict):

@@ -102,3 +102,20 @@ def test_server_argument_checks(dp):
     assert L.dpsnn_server_query(None, 1, C.byref(info)) == dp.E_INVAL
     L.dpsnn_server_destroy(None)
     assert C.sizeof(dp.dpsnn_job_info) == 8 + 4 + 4 + 4 + 4 + 8 + 4 * 8 + 8 + 160
+
+
+def test_checkpoint_header_checks(dp):
+    # rejected before any device work: too short, wrong magic, wrong version
+    import ctypes as C
+    h = C.c_void_p()
+    dev = dp.dpsnn_device()
+    for buf in (b"", b"DPSNNCK1", b"X" * 4096):
+        arr = (C.c_uint8 * max(1, len(buf))).from_buffer_copy(buf or b"\0")
+        rc = dp.lib().dpsnn_load(C.cast(arr, C.c_void_p), len(buf), C.byref(dev), C.byref(h))
+        assert rc == dp.E_INVAL, buf[:8]
+        assert not h.value
+    good = bytearray(b"DPSNNCK1" + b"\0" * 4088)
+    good[8] = 99  # version 99
+    arr = (C.c_uint8 * len(good)).from_buffer(good)
+    assert dp.lib().dpsnn_load(C.cast(arr, C.c_void_p), len(good), C.byref(dev), C.byref(h)) == dp.E_INVAL
+    assert "version" in dp.lib().dpsnn_last_error().decode()
