@@ -208,6 +208,11 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *          (default 2^32 - 1, i.e. always; 0 = never)
  *   key 8: steps per captured graph G, 0 .. 1024 (default 8; 0 = every step
  *          launched directly)
+ *   key 9: with the full window (key 2 = 1), workgroups that share one
+ *          source column's window by target slot, 1 .. 13 (default 1): each
+ *          reads all the column's events and delivers those whose target it
+ *          owns; a smaller LDS window per workgroup for latency-bound
+ *          networks with few columns
  * (sparse / dense choice in parentheses) */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 

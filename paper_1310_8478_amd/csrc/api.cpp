@@ -441,6 +441,10 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
             if (value > 1024) return fail(DPSNN_E_INVAL, "graph steps must be 0 (off) to 1024");
             tn.graph = value;
             return DPSNN_OK;
+        case 9:
+            if (value < 1 || value > 13) return fail(DPSNN_E_INVAL, "window split must be 1 to 13");
+            tn.split = value;
+            return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");
     }

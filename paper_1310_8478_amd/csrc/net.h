@@ -29,6 +29,7 @@ struct Tuning {
     uint32_t ltp_stage = 2;       // LDS source spike history in LTP: 0, 1, 2 auto (0 / 1)
     uint32_t fuse = 0xFFFFFFFFu;  // LTP + delivery as one kernel up to this many workgroups each
     uint32_t graph = 8;           // steps per captured graph; 0 = every step launched directly
+    uint32_t split = 1;           // workgroups sharing a column's full window by slot (1..13)
     size_t max_lds = 65536;
 };
 

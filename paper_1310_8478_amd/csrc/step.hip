@@ -284,12 +284,15 @@ __global__ __launch_bounds__(1024) void k_ltp(const NetDesc* __restrict__ nds,
 template <bool FIXED, int WIN, typename TgtT, int U>
 __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
                                              const uint2* __restrict__ bmap,
-                                             uint32_t allow_age, uint32_t nparts,
+                                             uint32_t allow_age, uint32_t nparts, uint32_t nsplit,
                                              unsigned long long* __restrict__ set_events,
                                              uint32_t tstep, uint32_t bid) {
-    // workgroup bid: part `part` of the column of map entry bid / nparts
-    const uint2 br = bmap[bid / nparts];
-    const uint32_t part = bid % nparts;
+    // workgroup bid: part `part` (a slice of the events) and window share sp
+    // of the column of map entry bid / (nparts * nsplit)
+    const uint32_t per = nparts * nsplit;
+    const uint2 br = bmap[bid / per];
+    const uint32_t part = (bid % per) % nparts;
+    const uint32_t sp = (bid % per) / nparts;
     const NetDesc& nd = nds[br.x];
     const Dims d = nd.d;
     const uint32_t t = nd.t0 + tstep;
@@ -313,7 +316,16 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     const uint32_t BS = blockDim.x;
     const uint32_t nwin = kSlots * d.Ncol;
     constexpr bool WINDOW = WIN != 0;
-    const uint32_t nlds = WIN == 1 ? nwin : (WIN == 2 ? d.Ncol : 0u);  // window entries
+    // with the full window the column's targets may be shared out over nsplit
+    // workgroups by slot: this one owns window indices [wlo, wlo + wspan),
+    // reads every event of its slice and delivers (and depresses) only the
+    // ones whose target it owns
+    const uint32_t s_lo = WIN == 1 ? (sp * kSlots) / nsplit : 0u;
+    const uint32_t s_hi = WIN == 1 ? ((sp + 1u) * kSlots) / nsplit : (uint32_t)kSlots;
+    const uint32_t wlo = s_lo * d.Ncol;
+    const uint32_t wspan = (s_hi - s_lo) * d.Ncol;
+    auto own = [&](uint32_t wi) { return wi - wlo < wspan; };
+    const uint32_t nlds = WIN == 1 ? wspan : (WIN == 2 ? d.Ncol : 0u);  // window entries
     // the window sums in fixed point in both modes: integer LDS atomics are
     // several times faster than fp32 LDS atomics on this GPU; the unordered
     // fp32 mode rounds each column's exact partial sum to fp32 once, at the
@@ -323,7 +335,7 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     // at 255 (255 also means "never" or "look it up"); staged when the
     // workgroup has enough events to reuse it
     uint8_t* age = lds_raw + win_bytes;
-    const size_t age_bytes = allow_age ? (((size_t)nwin + 15) & ~(size_t)15) : 0;
+    const size_t age_bytes = allow_age ? (((size_t)wspan + 15) & ~(size_t)15) : 0;
     uint32_t* pref = (uint32_t*)(lds_raw + win_bytes + age_bytes);  // [BS + 1]
     uint32_t* pos0 = pref + BS + 1;                      // [BS]
     uint32_t* excf = pos0 + BS;                          // [BS]
@@ -372,10 +384,11 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     // one delivery to window index wi with weight wv (excitatory: ex), and
     // its LTD added to dv
     auto deliver_one = [&](bool ex, uint32_t wi, float wv, float& dv) {
+        if (!own(wi)) return;
         ++ev_local;
         exc_events += ex ? 1u : 0u;
         if (WIN == 1 || (WIN == 2 && wi < nlds)) {
-            atomicAdd((unsigned long long*)&win64[wi],
+            atomicAdd((unsigned long long*)&win64[wi - wlo],
                       (unsigned long long)(ex ? to_fixed(wv) : q_inh));
         } else {
             if (FIXED) {
@@ -386,7 +399,7 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
             }
         }
         if (ex) {
-            const uint32_t ag = staged ? age[wi] : 255u;
+            const uint32_t ag = staged ? age[wi - wlo] : 255u;
             uint32_t dt = 0xFFFFFFFFu;
             if (ag < 255u) {
                 dt = ag + 1u;
@@ -420,10 +433,11 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
         const uint32_t c0 = (uint32_t)((uint64_t)c * d.Ncol * d.M - fb);
         const uint32_t cb = part_bound4(c0, c0 + d.Ncol * d.M, part, nparts);
         const uint32_t total = part_bound4(c0, c0 + d.Ncol * d.M, part + 1u, nparts) - cb;
-        if (allow_age && total >= nwin) {  // block-uniform
-            for (uint32_t x = tid; x < nwin; x += BS) {
-                const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
-                const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
+        if (allow_age && total >= wspan) {  // block-uniform
+            for (uint32_t x = tid; x < wspan; x += BS) {
+                const uint32_t xw = x + wlo;
+                const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, xw) : xw / d.Ncol;
+                const int32_t tq = t_last[cmap[sl] * d.Ncol + (xw - sl * d.Ncol)];
                 const int64_t ag = (tq == kNoSpike) ? 255 : (int64_t)t - tq;
                 age[x] = (uint8_t)(ag < 255 ? ag : 255);
             }
@@ -443,7 +457,7 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
                 const uint32_t wi = (uint32_t)tgt[p];
                 float dv = ex ? Dacc[p] : 0.0f;
                 deliver_one(ex, wi, ex ? w[p] : d.w_inh, dv);
-                if (ex) Dacc[p] = dv;
+                if (ex && own(wi)) Dacc[p] = dv;
             }
         }
         // aligned body: four consecutive positions per lane, vector loads
@@ -493,7 +507,17 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
                 deliver_one(m & 2u, wi[1], g.wv[q].y, g.dv[q].y);
                 deliver_one(m & 4u, wi[2], g.wv[q].z, g.dv[q].z);
                 deliver_one(m & 8u, wi[3], g.wv[q].w, g.dv[q].w);
-                if (m) *(float4*)(Dacc + g.p[q]) = g.dv[q];
+                // D of the excitatory positions whose target this workgroup owns
+                const uint32_t sm = m & ((own(wi[0]) ? 1u : 0u) | (own(wi[1]) ? 2u : 0u) |
+                                         (own(wi[2]) ? 4u : 0u) | (own(wi[3]) ? 8u : 0u));
+                if (sm == 0xFu) {
+                    *(float4*)(Dacc + g.p[q]) = g.dv[q];
+                } else if (sm) {
+                    if (sm & 1u) Dacc[g.p[q]] = g.dv[q].x;
+                    if (sm & 2u) Dacc[g.p[q] + 1] = g.dv[q].y;
+                    if (sm & 4u) Dacc[g.p[q] + 2] = g.dv[q].z;
+                    if (sm & 8u) Dacc[g.p[q] + 3] = g.dv[q].w;
+                }
             }
         };
         Grp A, B;
@@ -564,10 +588,11 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
                 }
                 uint32_t qlo, qhi;
                 part_slice(Q, part, nparts, qlo, qhi);
-                if (allow_age && !staged && 4u * (qhi - qlo) >= nwin) {  // block-uniform
-                    for (uint32_t x = tid; x < nwin; x += BS) {
-                        const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
-                        const int32_t tq = t_last[cmap[sl] * d.Ncol + (x - sl * d.Ncol)];
+                if (allow_age && !staged && 4u * (qhi - qlo) >= wspan) {  // block-uniform
+                    for (uint32_t x = tid; x < wspan; x += BS) {
+                        const uint32_t xw = x + wlo;
+                        const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, xw) : xw / d.Ncol;
+                        const int32_t tq = t_last[cmap[sl] * d.Ncol + (xw - sl * d.Ncol)];
                         const int64_t ag = (tq == kNoSpike) ? 255 : (int64_t)t - tq;
                         age[x] = (uint8_t)(ag < 255 ? ag : 255);
                     }
@@ -624,14 +649,18 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
                         if (m & 4u) deliver_one(ex, ti[q][2], wv[q].z, dv[q].z);
                         if (m & 8u) deliver_one(ex, ti[q][3], wv[q].w, dv[q].w);
                         if (ex) {
-                            // a partial quad may share positions with another run
-                            if (m == 0xFu) {
+                            // a partial quad may share positions with another
+                            // run; only owned targets' D is written
+                            const uint32_t sm =
+                                m & ((own(ti[q][0]) ? 1u : 0u) | (own(ti[q][1]) ? 2u : 0u) |
+                                     (own(ti[q][2]) ? 4u : 0u) | (own(ti[q][3]) ? 8u : 0u));
+                            if (sm == 0xFu) {
                                 *(float4*)(Dacc + p4[q]) = dv[q];
                             } else {
-                                if (m & 1u) Dacc[p4[q]] = dv[q].x;
-                                if (m & 2u) Dacc[p4[q] + 1] = dv[q].y;
-                                if (m & 4u) Dacc[p4[q] + 2] = dv[q].z;
-                                if (m & 8u) Dacc[p4[q] + 3] = dv[q].w;
+                                if (sm & 1u) Dacc[p4[q]] = dv[q].x;
+                                if (sm & 2u) Dacc[p4[q] + 1] = dv[q].y;
+                                if (sm & 4u) Dacc[p4[q] + 2] = dv[q].z;
+                                if (sm & 8u) Dacc[p4[q] + 3] = dv[q].w;
                             }
                         }
                     }
@@ -651,8 +680,9 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     if (WINDOW) {
         __syncthreads();
         for (uint32_t x = tid; x < nlds; x += BS) {
-            const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, x) : x / d.Ncol;
-            const uint32_t kg = cmap[sl] * d.Ncol + (x - sl * d.Ncol);
+            const uint32_t xw = x + wlo;
+            const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, xw) : xw / d.Ncol;
+            const uint32_t kg = cmap[sl] * d.Ncol + (xw - sl * d.Ncol);
             const long long val = win64[x];
             if (val != 0) {
                 if (FIXED) atomicAdd((unsigned long long*)&acc64[kg], (unsigned long long)val);
@@ -674,9 +704,11 @@ template <bool FIXED, int WIN, typename TgtT, int U>
 __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nds,
                                                   const uint2* __restrict__ bmap,
                                                   uint32_t allow_age, uint32_t nparts,
+                                                  uint32_t nsplit,
                                                   unsigned long long* __restrict__ set_events,
                                                   uint32_t tstep) {
-    deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, set_events, tstep, blockIdx.x);
+    deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, nsplit, set_events, tstep,
+                                      blockIdx.x);
 }
 
 // LTP and delivery of one step in a single launch, for launches small enough
@@ -687,13 +719,13 @@ template <bool FIXED, int WIN, typename TgtT, int U>
 __global__ __launch_bounds__(1024) void k_ltp_deliver(const NetDesc* __restrict__ nds,
                                                       const uint2* __restrict__ bmap,
                                                       uint32_t allow_stage, uint32_t allow_age,
-                                                      uint32_t nparts,
+                                                      uint32_t nparts, uint32_t nsplit,
                                                       unsigned long long* __restrict__ set_events,
                                                       uint32_t tstep, uint32_t n_ltp) {
     if (blockIdx.x < n_ltp)
         ltp_body<4>(nds, bmap, allow_stage, nparts, tstep, blockIdx.x);
     else
-        deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, set_events, tstep,
+        deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, nsplit, set_events, tstep,
                                           blockIdx.x - n_ltp);
 }
 
@@ -1058,32 +1090,37 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
     // one thread per raster word of a column and delay chunk
     const uint32_t BS = std::max<uint32_t>(tune.deliver_block, ((L.max_w + 63) / 64) * 64);
     const size_t esz = 8;  // fixed-point window entries in every mode
-    const size_t win_full = (((size_t)kSlots * L.max_ncol * esz) + 15) & ~(size_t)15;
+    // the full window may be shared out by slot over nsplit workgroups
+    const uint32_t split_req = std::min<uint32_t>(std::max<uint32_t>(tune.split, 1u), (uint32_t)kSlots);
+    const uint32_t share = (kSlots + split_req - 1u) / split_req;  // most slots of one share
+    const size_t win_full = (((size_t)share * L.max_ncol * esz) + 15) & ~(size_t)15;
     const size_t win_own = (((size_t)L.max_ncol * esz) + 15) & ~(size_t)15;
-    const size_t agew = (((size_t)kSlots * L.max_ncol) + 15) & ~(size_t)15;
     const size_t base = ((size_t)3 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
     // window mode: the requested one if it fits, else the own-column window
     // if that fits, else none
     int wmode = 0;
     if (tune.window == 1 && win_full + base + 256 <= tune.max_lds) wmode = 1;
     else if (tune.window >= 1 && win_own + base + 256 <= tune.max_lds) wmode = 2;
+    const uint32_t nsplit = wmode == 1 ? split_req : 1u;
+    const size_t agew = (((size_t)(wmode == 1 ? share : (uint32_t)kSlots) * L.max_ncol) + 15) & ~(size_t)15;
     const size_t lds0 = (wmode == 1 ? win_full : (wmode == 2 ? win_own : 0)) + base;
     const uint32_t allow_age = (tune.age && lds0 + agew + 256 <= tune.max_lds) ? 1u : 0u;
     const size_t lds = lds0 + (allow_age ? agew : 0);
-    const uint32_t nblk = L.n_col * nparts;
+    const uint32_t n_ltp = L.n_col * nparts;
+    const uint32_t nblk = n_ltp * nsplit;
 #define DPSNN_DELIVER(FX, WN, UU)                                                              \
     do {                                                                                       \
         if (fl.on) {                                                                           \
             const size_t lf = std::max(lds, fl.lds);                                           \
             allow_lds(k_ltp_deliver<FX, WN, TgtT, UU>, lf);                                    \
-            hipLaunchKernelGGL((k_ltp_deliver<FX, WN, TgtT, UU>), dim3(2 * nblk), dim3(BS), lf, \
-                               stream, L.descs, L.bmap_col, fl.allow_stage, allow_age, nparts, \
-                               L.ev_count, tstep, nblk);                                      \
+            hipLaunchKernelGGL((k_ltp_deliver<FX, WN, TgtT, UU>), dim3(n_ltp + nblk), dim3(BS),  \
+                               lf, stream, L.descs, L.bmap_col, fl.allow_stage, allow_age,     \
+                               nparts, nsplit, L.ev_count, tstep, n_ltp);                      \
         } else {                                                                               \
             allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                       \
             hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(nblk), dim3(BS), lds,       \
-                               stream, L.descs, L.bmap_col, allow_age, nparts, L.ev_count,     \
-                               tstep);                                                         \
+                               stream, L.descs, L.bmap_col, allow_age, nparts, nsplit,         \
+                               L.ev_count, tstep);                                             \
         }                                                                                      \
     } while (0)
 #define DPSNN_DELIVER_W(FX, UU)                                                                \
@@ -1206,7 +1243,7 @@ namespace {
 bool same_shapes(const Tuning& a, const Tuning& b) {
     return a.deliver_block == b.deliver_block && a.ltp_block == b.ltp_block && a.window == b.window &&
            a.unroll == b.unroll && a.age == b.age && a.parts == b.parts && a.ltp_stage == b.ltp_stage &&
-           a.fuse == b.fuse && a.max_lds == b.max_lds;
+           a.fuse == b.fuse && a.split == b.split && a.max_lds == b.max_lds;
 }
 
 // The kernels of one step of every network of the set at t = t0 + tstep, in

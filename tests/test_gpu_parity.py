@@ -203,6 +203,8 @@ TUNINGS = [
     ((5, 1),), ((5, 3),), ((5, 7), (2, 0)), ((5, 64), (0, 256), (1, 512)),
     ((2, 2),), ((2, 2), (6, 0), (0, 512), (1, 256)), ((2, 2), (5, 5), (3, 4)), ((6, 0),),
     ((7, 0),), ((7, 0), (5, 3), (3, 8)),
+    ((9, 2), (2, 1)), ((9, 3), (2, 1), (4, 1), (0, 512), (1, 512)), ((9, 13), (2, 1), (5, 2)),
+    ((9, 2), (2, 1), (7, 0), (3, 1)),
 ]
 
 
@@ -214,7 +216,8 @@ def test_dense_regime_column_parts(dp):
     _say("dense regime, column parts 1 vs 13 vs 200")
     ref = gpu_run(dp, cfg, T, tuning=((5, 1),), conn=False)
     assert (np.bincount(ref["tt"], minlength=T + 1)[110:] == 2500).sum() >= 20
-    for tn in (((5, 13),), ((5, 200),), ((5, 9), (2, 2), (6, 0))):
+    for tn in (((5, 13),), ((5, 200),), ((5, 9), (2, 2), (6, 0)), ((9, 2), (2, 1)),
+               ((9, 5), (2, 1), (5, 3), (4, 1))):
         g = gpu_run(dp, cfg, T, tuning=tn, conn=False)
         assert_bitexact(g, ref, conn=False)
         assert g["stats"]["events"] == ref["stats"]["events"]
