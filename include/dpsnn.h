@@ -192,8 +192,9 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *   key 0: delivery workgroup size 256, 512, 1024; 0 = automatic (256 / 1024)
  *   key 1: LTP workgroup size 256, 512, 1024; 0 = automatic (256 / 1024)
  *   key 2: LDS current window in delivery: 1 = over all 13 reachable
- *          columns, 2 = over the own column only, 0 = off; 3 = automatic
- *          (2 / 1); a window that does not fit in LDS falls back to 2, then 0
+ *          columns, 2 = a partial window (the own column and the nearest
+ *          slots, key 10), 0 = off; 3 = automatic (2 / 1); a window that does
+ *          not fit in LDS falls back to 2, then 0
  *   key 3: delivery unroll U = 1, 2, 4 or 8 (default 4): each lane keeps
  *          max(1, U / 2) quads of 4 consecutive synapses in flight
  *   key 4: LDS copy of the targets' spike ages in delivery: 1 on, 0 off,
@@ -213,6 +214,9 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *          reads all the column's events and delivers those whose target it
  *          owns; a smaller LDS window per workgroup for latency-bound
  *          networks with few columns
+ *   key 10: slots of the partial window (key 2 = 2), 1 .. 13: the own column
+ *          first, then the nearest neighbour slots; events to other slots
+ *          take global atomics; 0 = automatic (3 / 1)
  * (sparse / dense choice in parentheses) */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 

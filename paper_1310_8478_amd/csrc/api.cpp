@@ -445,6 +445,10 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
             if (value < 1 || value > 13) return fail(DPSNN_E_INVAL, "window split must be 1 to 13");
             tn.split = value;
             return DPSNN_OK;
+        case 10:
+            if (value > 13) return fail(DPSNN_E_INVAL, "partial window slots must be 0 (automatic) to 13");
+            tn.own_slots = value;
+            return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");
     }

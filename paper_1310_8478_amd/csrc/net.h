@@ -22,7 +22,7 @@ constexpr uint32_t kXcds = 8;  // accelerator dies (XCDs) of the GPU, each with 
 struct Tuning {
     uint32_t deliver_block = 0;   // 256, 512, 1024; 0 auto (sparse 256, dense 1024)
     uint32_t ltp_block = 0;       // 256, 512, 1024; 0 auto (sparse 256, dense 1024)
-    uint32_t window = 3;          // 0 off, 1 all 13 columns, 2 own column; 3 auto (2 / 1)
+    uint32_t window = 3;          // 0 off, 1 all 13 columns, 2 partial (own_slots); 3 auto (2 / 1)
     uint32_t unroll = 4;           // events (quads) in flight per lane in delivery
     uint32_t age = 2;             // LDS target spike ages: 0 off, 1 on, 2 auto (off / on)
     uint32_t parts = 0;           // workgroups per column (0: chosen per launch set)
@@ -30,6 +30,7 @@ struct Tuning {
     uint32_t fuse = 0xFFFFFFFFu;  // LTP + delivery as one kernel up to this many workgroups each
     uint32_t graph = 8;           // steps per captured graph; 0 = every step launched directly
     uint32_t split = 1;           // workgroups sharing a column's full window by slot (1..13)
+    uint32_t own_slots = 0;       // slots of the partial window (window 2), 1..13; 0 auto (3 / 1)
     size_t max_lds = 65536;
 };
 

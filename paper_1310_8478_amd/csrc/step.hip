@@ -285,6 +285,7 @@ template <bool FIXED, int WIN, typename TgtT, int U>
 __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
                                              const uint2* __restrict__ bmap,
                                              uint32_t allow_age, uint32_t nparts, uint32_t nsplit,
+                                             uint32_t wslots,
                                              unsigned long long* __restrict__ set_events,
                                              uint32_t tstep, uint32_t bid) {
     // workgroup bid: part `part` (a slice of the events) and window share sp
@@ -325,7 +326,9 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     const uint32_t wlo = s_lo * d.Ncol;
     const uint32_t wspan = (s_hi - s_lo) * d.Ncol;
     auto own = [&](uint32_t wi) { return wi - wlo < wspan; };
-    const uint32_t nlds = WIN == 1 ? wspan : (WIN == 2 ? d.Ncol : 0u);  // window entries
+    // the partial window (WIN 2) covers the first wslots slots: the own
+    // column, then the nearest neighbour rings
+    const uint32_t nlds = WIN == 1 ? wspan : (WIN == 2 ? wslots * d.Ncol : 0u);  // window entries
     // the window sums in fixed point in both modes: integer LDS atomics are
     // several times faster than fp32 LDS atomics on this GPU; the unordered
     // fp32 mode rounds each column's exact partial sum to fp32 once, at the
@@ -704,11 +707,11 @@ template <bool FIXED, int WIN, typename TgtT, int U>
 __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nds,
                                                   const uint2* __restrict__ bmap,
                                                   uint32_t allow_age, uint32_t nparts,
-                                                  uint32_t nsplit,
+                                                  uint32_t nsplit, uint32_t wslots,
                                                   unsigned long long* __restrict__ set_events,
                                                   uint32_t tstep) {
-    deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, nsplit, set_events, tstep,
-                                      blockIdx.x);
+    deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, nsplit, wslots, set_events,
+                                      tstep, blockIdx.x);
 }
 
 // LTP and delivery of one step in a single launch, for launches small enough
@@ -720,13 +723,14 @@ __global__ __launch_bounds__(1024) void k_ltp_deliver(const NetDesc* __restrict_
                                                       const uint2* __restrict__ bmap,
                                                       uint32_t allow_stage, uint32_t allow_age,
                                                       uint32_t nparts, uint32_t nsplit,
+                                                      uint32_t wslots,
                                                       unsigned long long* __restrict__ set_events,
                                                       uint32_t tstep, uint32_t n_ltp) {
     if (blockIdx.x < n_ltp)
         ltp_body<4>(nds, bmap, allow_stage, nparts, tstep, blockIdx.x);
     else
-        deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, nsplit, set_events, tstep,
-                                          blockIdx.x - n_ltp);
+        deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, nsplit, wslots, set_events,
+                                          tstep, blockIdx.x - n_ltp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1094,7 +1098,8 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
     const uint32_t split_req = std::min<uint32_t>(std::max<uint32_t>(tune.split, 1u), (uint32_t)kSlots);
     const uint32_t share = (kSlots + split_req - 1u) / split_req;  // most slots of one share
     const size_t win_full = (((size_t)share * L.max_ncol * esz) + 15) & ~(size_t)15;
-    const size_t win_own = (((size_t)L.max_ncol * esz) + 15) & ~(size_t)15;
+    const uint32_t wslots = std::min<uint32_t>(std::max<uint32_t>(tune.own_slots, 1u), (uint32_t)kSlots);
+    const size_t win_own = (((size_t)wslots * L.max_ncol * esz) + 15) & ~(size_t)15;
     const size_t base = ((size_t)3 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
     // window mode: the requested one if it fits, else the own-column window
     // if that fits, else none
@@ -1115,11 +1120,11 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
             allow_lds(k_ltp_deliver<FX, WN, TgtT, UU>, lf);                                    \
             hipLaunchKernelGGL((k_ltp_deliver<FX, WN, TgtT, UU>), dim3(n_ltp + nblk), dim3(BS),  \
                                lf, stream, L.descs, L.bmap_col, fl.allow_stage, allow_age,     \
-                               nparts, nsplit, L.ev_count, tstep, n_ltp);                      \
+                               nparts, nsplit, wslots, L.ev_count, tstep, n_ltp);              \
         } else {                                                                               \
             allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                       \
             hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(nblk), dim3(BS), lds,       \
-                               stream, L.descs, L.bmap_col, allow_age, nparts, nsplit,         \
+                               stream, L.descs, L.bmap_col, allow_age, nparts, nsplit, wslots, \
                                L.ev_count, tstep);                                             \
         }                                                                                      \
     } while (0)
@@ -1235,6 +1240,7 @@ Tuning effective_tuning(const LaunchSet& L, const Tuning& tune) {
     if (t.window == 3u) t.window = sparse ? 2u : 1u;
     if (t.age == 2u) t.age = sparse ? 0u : 1u;
     if (t.ltp_stage == 2u) t.ltp_stage = sparse ? 0u : 1u;
+    if (t.own_slots == 0u) t.own_slots = sparse ? 3u : 1u;
     return t;
 }
 
@@ -1243,7 +1249,8 @@ namespace {
 bool same_shapes(const Tuning& a, const Tuning& b) {
     return a.deliver_block == b.deliver_block && a.ltp_block == b.ltp_block && a.window == b.window &&
            a.unroll == b.unroll && a.age == b.age && a.parts == b.parts && a.ltp_stage == b.ltp_stage &&
-           a.fuse == b.fuse && a.split == b.split && a.max_lds == b.max_lds;
+           a.fuse == b.fuse && a.split == b.split && a.own_slots == b.own_slots &&
+           a.max_lds == b.max_lds;
 }
 
 // The kernels of one step of every network of the set at t = t0 + tstep, in

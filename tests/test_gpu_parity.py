@@ -205,6 +205,7 @@ TUNINGS = [
     ((7, 0),), ((7, 0), (5, 3), (3, 8)),
     ((9, 2), (2, 1)), ((9, 3), (2, 1), (4, 1), (0, 512), (1, 512)), ((9, 13), (2, 1), (5, 2)),
     ((9, 2), (2, 1), (7, 0), (3, 1)),
+    ((2, 2), (10, 5)), ((2, 2), (10, 13), (0, 256), (1, 256)), ((2, 2), (10, 3), (4, 1), (7, 0)),
 ]
 
 
@@ -238,6 +239,10 @@ def test_sparse_regime_shapes_invariance(dp):
     assert_bitexact(g, ref, conn=False)
     assert g["stats"]["events"] == ref["stats"]["events"]
     assert g["stats"]["ltp_visits"] == ref["stats"]["ltp_visits"]
+    # the sparse shapes with a partial window over the own column and the
+    # first neighbour ring
+    g5 = gpu_run(dp, cfg, T, tuning=((10, 5),), conn=False)
+    assert_bitexact(g5, ref, conn=False)
 
 
 @pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
@@ -302,6 +307,33 @@ def test_read_errors(dp):
         n = C.c_size_t()
         rc = dp.lib().dpsnn_read_spikes(net.h, 1, 31, None, None, 0, C.byref(n))
         assert rc in (0, dp.E_BUFSZ)
+    finally:
+        net.close()
+
+
+def test_tuning_and_step_arguments(dp):
+    # knob values outside their ranges are refused and change nothing; a
+    # zero-step call is a no-op; results are those of the defaults
+    ref = gpu_run(dp, W.tiny(weight_update_period=40), 60, conn=False)
+    net = dp.Network(W.tiny(weight_update_period=40))
+    try:
+        for key, val in ((0, 300), (1, 100), (2, 4), (3, 3), (4, 3), (5, 1025), (6, 3),
+                         (8, 1025), (9, 0), (9, 14), (10, 14), (11, 1)):
+            with pytest.raises(dp.DpsnnError) as e:
+                net.set_tuning(key, val)
+            assert e.value.code == dp.E_INVAL, (key, val)
+        net.step(0)
+        assert net.t == 0
+        net.step(60)
+        net.step(0)
+        net.sync()
+        assert net.t == 60
+        tt, ii = net.read_spikes(1, 61)
+        np.testing.assert_array_equal(tt, ref["tt"])
+        np.testing.assert_array_equal(ii, ref["ii"])
+        with pytest.raises(dp.DpsnnError) as e:
+            net.autotune(0)
+        assert e.value.code == dp.E_INVAL
     finally:
         net.close()
 
