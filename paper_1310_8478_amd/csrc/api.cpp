@@ -356,6 +356,7 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
         }
         L.avg_nwin = L.n_col ? (double)kSlots * neurons / (double)L.n_col : 0.0;
         L.per_col = L.n_col ? est / (double)L.n_col : 0.0;  // carried over from earlier sets
+        L.sparse = L.per_col < L.avg_nwin;
         L.steps = L.copy_steps = L.base_steps = L.base_count = 0;
         L.copy_pending = false;
     }

@@ -72,6 +72,9 @@ struct LaunchSet {
     bool copy_pending = false;
     uint64_t steps = 0, copy_steps = 0, base_steps = 0, base_count = 0;
     double per_col = 0.0;
+    // regime with hysteresis: sparse below 0.8 window entries per column, dense
+    // above 1.0, unchanged in between
+    bool sparse = true;
     // captured graph of graph_steps steps (launch shapes graph_tune), and the
     // stream it was captured on
     hipGraphExec_t graph = nullptr;

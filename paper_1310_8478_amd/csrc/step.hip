@@ -1198,8 +1198,8 @@ void Timers::release() {
 // steps after it was enqueued is waited for, which keeps the host at most
 // about 16 steps ahead of the device and the estimate at most that stale.
 void sample_regime(LaunchSet& L, hipStream_t stream, Net* const* members) {
-    // sets under 2048 columns always take the dense shapes: nothing to measure
-    if (!L.ev_host || !L.ev_copied || L.n_col < 2048u) return;
+    // sets under 64 columns always take the dense shapes: nothing to measure
+    if (!L.ev_host || !L.ev_copied || L.n_col < 64u) return;
     bool landed = false;
     if (L.copy_pending) {
         hipError_t q = hipEventQuery(L.ev_copied);
@@ -1212,6 +1212,8 @@ void sample_regime(LaunchSet& L, hipStream_t stream, Net* const* members) {
             L.per_col = (double)(v - L.base_count) / (double)(L.copy_steps - L.base_steps) /
                         (double)L.n_col;
             for (uint32_t k = 0; k < L.K; ++k) members[k]->per_col = L.per_col;
+            if (L.sparse && L.per_col > L.avg_nwin) L.sparse = false;
+            else if (!L.sparse && L.per_col < 0.8 * L.avg_nwin) L.sparse = true;
         }
         L.base_count = v;
         L.base_steps = L.copy_steps;
@@ -1230,17 +1232,30 @@ void sample_regime(LaunchSet& L, hipStream_t stream, Net* const* members) {
 // The launch shapes for this step: explicit knobs as set, automatic ones by
 // the set's regime.  Sparse shapes (small LDS, 256-thread workgroups, several
 // per CU) pay off when each source column delivers fewer events than its
-// current window has entries and there are many columns per CU; otherwise
-// the full window and 1024-thread workgroups are faster.
+// current window has entries and there are enough workgroups (at least 512
+// column parts, from at least 64 columns) to fill the chip; otherwise the
+// full window and 1024-thread workgroups are faster.
 Tuning effective_tuning(const LaunchSet& L, const Tuning& tune) {
     Tuning t = tune;
-    const bool sparse = L.n_col >= 2048u && L.per_col < L.avg_nwin;
+    const uint64_t wgs = (uint64_t)L.n_col * column_parts(L, tune);
+    const bool many = L.n_col >= 2048u || (L.n_col >= 64u && wgs >= 512u);
+    const bool sparse = many && L.sparse;
+    // sparse shapes split the columns of sets of 512 .. 1023 columns in two
+    // (smaller sets keep the parts above: measured best)
+    if (sparse && !t.parts && L.sum_mode != DPSNN_SUM_ORDERED && L.n_col >= 512u &&
+        L.n_col < 1024u) {
+        const uint64_t want = (1024u + L.n_col - 1u) / L.n_col;
+        const uint64_t cap = std::max<uint64_t>(1u, L.min_col_syn / 8192u);
+        t.parts = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, cap), 1024u);
+    }
     if (!t.deliver_block) t.deliver_block = sparse ? 256u : 1024u;
     if (!t.ltp_block) t.ltp_block = sparse ? 256u : 1024u;
     if (t.window == 3u) t.window = sparse ? 2u : 1u;
     if (t.age == 2u) t.age = sparse ? 0u : 1u;
     if (t.ltp_stage == 2u) t.ltp_stage = sparse ? 0u : 1u;
-    if (t.own_slots == 0u) t.own_slots = sparse ? 3u : 1u;
+    // the partial window: the own column alone on grids below 2048 columns,
+    // the own column and two neighbour slots on larger ones (measured)
+    if (t.own_slots == 0u) t.own_slots = (sparse && L.n_col >= 2048u) ? 3u : 1u;
     return t;
 }
 
