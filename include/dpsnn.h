@@ -248,7 +248,9 @@ int dpsnn_checkpoint_bytes(dpsnn_net *net, uint64_t *bytes);
 int dpsnn_save(dpsnn_net *net, void *buf, uint64_t cap);
 /* Build a network on *dev from a checkpoint of `size` bytes (as written by
  * dpsnn_save) and restore its state; DPSNN_E_INVAL if buf is not a whole,
- * consistent checkpoint of this format.  *out is owned by the caller. */
+ * consistent checkpoint of this format: header, configuration, total size
+ * and raster (no spike bit beyond a column's last neuron) are checked on the
+ * host before any device work.  *out is owned by the caller. */
 int dpsnn_load(const void *buf, uint64_t size, const dpsnn_device *dev, dpsnn_net **out);
 
 void dpsnn_destroy(dpsnn_net *net);

@@ -569,26 +569,52 @@ struct CkptPart {
 
 size_t pad16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// Byte sizes of the checkpoint arrays, in file order; the raster ring is
+// entry kCkptRing.
+constexpr size_t kCkptRing = 4;
+
+std::vector<size_t> ckpt_sizes(uint64_t N, uint64_t C, uint64_t W, uint64_t R, uint64_t S,
+                               uint64_t stim_n) {
+    return {4 * N, 4 * N, sizeof(uint2) * N, 4 * N, sizeof(uint64_t) * R * C * W,
+            sizeof(DevStats) * 64, 4 * S, 4 * S, 4 * S, 4 * stim_n, 4 * stim_n, 4 * stim_n};
+}
+
 std::vector<CkptPart> ckpt_parts(const Net& n, uint64_t stim_n) {
-    const size_t N = n.d.N;
-    return {{n.v, 4 * N},
-            {n.u, 4 * N},
-            {n.hist, sizeof(uint2) * N},
-            {n.t_last, 4 * N},
-            {n.ring, sizeof(uint64_t) * (size_t)n.d.R * n.d.C * n.d.W},
-            {n.stats, sizeof(DevStats) * 64},
-            {n.w, 4 * (size_t)n.S},
-            {n.Dacc, 4 * (size_t)n.S},
-            {nullptr, 4 * (size_t)n.S},  // P in the forward layout (through a buffer)
-            {n.stim_t, 4 * (size_t)stim_n},
-            {n.stim_id, 4 * (size_t)stim_n},
-            {n.stim_mv, 4 * (size_t)stim_n}};
+    const std::vector<size_t> b = ckpt_sizes(n.d.N, n.d.C, n.d.W, n.d.R, n.S, stim_n);
+    void* const dev[] = {n.v, n.u, n.hist, n.t_last, n.ring, n.stats, n.w, n.Dacc,
+                         nullptr,  // P in the forward layout (through a buffer)
+                         n.stim_t, n.stim_id, n.stim_mv};
+    std::vector<CkptPart> parts(b.size());
+    for (size_t k = 0; k < b.size(); ++k) parts[k] = {dev[k], b[k]};
+    return parts;
+}
+
+uint64_t ckpt_total(const std::vector<size_t>& sizes) {
+    uint64_t tot = pad16(sizeof(CkptHeader));
+    for (size_t b : sizes) tot += pad16(b);
+    return tot;
 }
 
 uint64_t ckpt_total(const std::vector<CkptPart>& parts) {
     uint64_t tot = pad16(sizeof(CkptHeader));
     for (const CkptPart& q : parts) tot += pad16(q.bytes);
     return tot;
+}
+
+// The raster words of a checkpoint hold no spike beyond a column's last
+// neuron (delivery decodes source neurons from these bits).
+bool ckpt_raster_in_range(const unsigned char* buf, const std::vector<size_t>& sizes,
+                          const Derived& d) {
+    if (d.Ncol % 64u == 0u) return true;
+    const uint64_t keep = (1ull << (d.Ncol % 64u)) - 1ull;
+    size_t off = pad16(sizeof(CkptHeader));
+    for (size_t k = 0; k < kCkptRing; ++k) off += pad16(sizes[k]);
+    for (uint64_t rc = 0; rc < (uint64_t)d.R * d.C; ++rc) {
+        uint64_t word;
+        std::memcpy(&word, buf + off + ((rc + 1) * d.W - 1) * sizeof(uint64_t), sizeof(word));
+        if (word & ~keep) return false;
+    }
+    return true;
 }
 
 }  // namespace
@@ -1117,6 +1143,12 @@ int dpsnn_load(const void* buf, uint64_t size, const dpsnn_device* dev, dpsnn_ne
     if (hd.cfg.raster_steps != dv.R || hd.t >= (1ull << 31) || hd.stim_n > 0xFFFFFFFFull ||
         hd.total_bytes != size)
         return fail(DPSNN_E_INVAL, "inconsistent checkpoint header");
+    // contents are checked on the host, before any device work
+    const std::vector<size_t> sizes = ckpt_sizes(dv.N, dv.C, dv.W, dv.R, dv.S, hd.stim_n);
+    if (ckpt_total(sizes) != size)
+        return fail(DPSNN_E_INVAL, "checkpoint size does not match its configuration");
+    if (!ckpt_raster_in_range(static_cast<const unsigned char*>(buf), sizes, dv))
+        return fail(DPSNN_E_INVAL, "checkpoint raster has spikes beyond a column's last neuron");
     dpsnn_net* h = nullptr;
     rc = dpsnn_build_network(&hd.cfg, dev, &h);
     if (rc) return rc;

@@ -119,3 +119,63 @@ def test_checkpoint_header_checks(dp):
     arr = (C.c_uint8 * len(good)).from_buffer(good)
     assert dp.lib().dpsnn_load(C.cast(arr, C.c_void_p), len(good), C.byref(dev), C.byref(h)) == dp.E_INVAL
     assert "version" in dp.lib().dpsnn_last_error().decode()
+
+
+def _checkpoint_image(dp, cfg, R, extra=0):
+    """A checkpoint of `cfg` with zero state, laid out as dpsnn_save writes it
+    (header, then each array padded to 16 bytes); returns (buffer, offset of
+    the raster ring, raster words per column)."""
+    import struct
+    c = dp.to_config(dict(cfg, raster_steps=R))
+    Ncol = cfg["neurons_per_column"]
+    C_ = cfg["grid_x"] * cfg["grid_y"]
+    N, W_ = C_ * Ncol, (Ncol + 63) // 64
+    S = N * cfg["synapses_per_neuron"]
+    pad = lambda x: (x + 15) & ~15
+    head = 16 + C.sizeof(c) + 32
+    sizes = [4 * N, 4 * N, 8 * N, 4 * N, 8 * R * C_ * W_, 32 * 64, 4 * S, 4 * S, 4 * S, 0, 0, 0]
+    total = pad(head) + sum(pad(b) for b in sizes) + extra
+    buf = bytearray(total)
+    buf[0:8] = b"DPSNNCK1"
+    buf[8:16] = struct.pack("<II", 1, head)
+    buf[16:16 + C.sizeof(c)] = bytes(c)
+    buf[16 + C.sizeof(c):head] = struct.pack("<QQQQ", 5, 0, 0, total)
+    ring = pad(head) + sum(pad(b) for b in sizes[:4])
+    return buf, ring, W_
+
+
+def _load(dp, buf):
+    h = C.c_void_p()
+    dev = dp.dpsnn_device()
+    arr = (C.c_uint8 * len(buf)).from_buffer(buf)
+    rc = dp.lib().dpsnn_load(C.cast(arr, C.c_void_p), len(buf), C.byref(dev), C.byref(h))
+    if rc == 0:                     # loaded (a device is present): no error message
+        dp.lib().dpsnn_destroy(h)
+        return rc, ""
+    return rc, dp.lib().dpsnn_last_error().decode()
+
+
+def test_checkpoint_contents_checked_on_host(dp):
+    # ragged 65-neuron columns: the last raster word of a column has one valid bit
+    cfg = W.make_config(grid_x=2, grid_y=1, neurons_per_column=65, synapses_per_neuron=3)
+    R = 24
+    buf, ring, W_ = _checkpoint_image(dp, cfg, R)
+    rc, msg = _load(dp, buf)
+    assert "raster" not in msg and "size" not in msg, msg   # passes the host checks
+    # a spike bit beyond the column's last neuron, in any slot or column
+    for slot, col, bit in ((0, 0, 1), (R - 1, 1, 63), (7, 1, 5)):
+        bad = bytearray(buf)
+        pos = ring + ((slot * 2 + col) * W_ + W_ - 1) * 8
+        bad[pos:pos + 8] = (1 << bit).to_bytes(8, "little")
+        rc, msg = _load(dp, bad)
+        assert rc == dp.E_INVAL and "raster" in msg, (slot, col, bit, rc, msg)
+    # the valid bit of the last word is accepted by the host checks
+    ok = bytearray(buf)
+    pos = ring + (W_ - 1) * 8
+    ok[pos:pos + 8] = (1).to_bytes(8, "little")
+    rc, msg = _load(dp, ok)
+    assert "raster" not in msg, msg
+    # a total that disagrees with the configuration's array sizes
+    big, _, _ = _checkpoint_image(dp, cfg, R, extra=16)
+    rc, msg = _load(dp, big)
+    assert rc == dp.E_INVAL and "size" in msg, msg
