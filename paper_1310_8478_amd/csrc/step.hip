@@ -822,6 +822,50 @@ __global__ __launch_bounds__(256) void k_deliver_seq(const NetDesc* __restrict__
 // state); v takes two 0.5 ms sub-steps and u one 1 ms step (Sec. 3).
 // One thread per neuron; each wavefront covers one 64-neuron raster word.
 // ---------------------------------------------------------------------------
+// Events per target up to which the ordered fold selects keys one by one
+// (O(n^2) reads, no writes); above it the target's events are sorted first.
+constexpr uint32_t kSelectFold = 32;
+
+// One target's n events of a step, sorted in place by key (weights move
+// with their keys): heapsort, O(n log n) in the target's own slot range.
+__device__ __forceinline__ void sift_events(unsigned long long* __restrict__ key,
+                                            float* __restrict__ wt, uint32_t r, uint32_t end) {
+    const unsigned long long rk = key[r];
+    const float rw = wt[r];
+    for (;;) {
+        uint32_t ch = 2u * r + 1u;
+        if (ch >= end) break;
+        unsigned long long ck = key[ch];
+        if (ch + 1u < end) {
+            const unsigned long long k2 = key[ch + 1u];
+            if (k2 > ck) {
+                ch += 1u;
+                ck = k2;
+            }
+        }
+        if (ck <= rk) break;
+        key[r] = ck;
+        wt[r] = wt[ch];
+        r = ch;
+    }
+    key[r] = rk;
+    wt[r] = rw;
+}
+
+__device__ __forceinline__ void sort_events(unsigned long long* __restrict__ key,
+                                            float* __restrict__ wt, uint32_t n) {
+    for (uint32_t s = n / 2u; s-- > 0u;) sift_events(key, wt, s, n);
+    for (uint32_t end = n; end > 1u; --end) {
+        const unsigned long long k0 = key[0];
+        const float w0 = wt[0];
+        key[0] = key[end - 1u];
+        wt[0] = wt[end - 1u];
+        key[end - 1u] = k0;
+        wt[end - 1u] = w0;
+        sift_events(key, wt, 0u, end - 1u);
+    }
+}
+
 template <uint32_t MODE>
 __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
                                                 const uint2* __restrict__ bmap, uint32_t tstep) {
@@ -841,8 +885,8 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
     const float* __restrict__ stim_mv = nd.stim_mv;
     uint32_t* __restrict__ ev_cnt = nd.ev_cnt;
     const uint32_t* __restrict__ ev_start = nd.ev_start;
-    const unsigned long long* __restrict__ ev_key = nd.ev_key;
-    const float* __restrict__ ev_w = nd.ev_w;
+    unsigned long long* __restrict__ ev_key = nd.ev_key;
+    float* __restrict__ ev_w = nd.ev_w;
     uint32_t* __restrict__ cursor = nd.cursor;
     DevStats* __restrict__ stats = nd.stats;
     // stimulus entries of step t: [sb, se) of the step-sorted list
@@ -908,19 +952,26 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
             }
         }
         if (MODE == DPSNN_SUM_ORDERED) {
-            // canonical-order fold of this step's deliveries
+            // canonical-order fold of this step's deliveries (keys are
+            // distinct): few events are taken by repeated selection of the
+            // next key (reads only); many are first sorted in place
             const uint32_t b0 = ev_start[k];
             const uint32_t ne = ev_cnt[k];
-            unsigned long long prev = 0ull;
-            for (uint32_t r = 0; r < ne; ++r) {
-                unsigned long long best = ~0ull;
-                float bw = 0.0f;
-                for (uint32_t x = 0; x < ne; ++x) {
-                    const unsigned long long kk = ev_key[b0 + x];
-                    if (kk > prev && kk < best) { best = kk; bw = ev_w[b0 + x]; }
+            if (ne <= kSelectFold) {
+                unsigned long long prev = 0ull;
+                for (uint32_t r = 0; r < ne; ++r) {
+                    unsigned long long best = ~0ull;
+                    float bw = 0.0f;
+                    for (uint32_t x = 0; x < ne; ++x) {
+                        const unsigned long long kk = ev_key[b0 + x];
+                        if (kk > prev && kk < best) { best = kk; bw = ev_w[b0 + x]; }
+                    }
+                    a32 = a32 + bw;
+                    prev = best;
                 }
-                a32 = a32 + bw;
-                prev = best;
+            } else {
+                sort_events(ev_key + b0, ev_w + b0, ne);
+                for (uint32_t x = 0; x < ne; ++x) a32 = a32 + ev_w[b0 + x];
             }
             ev_cnt[k] = 0u;
             cursor[k] = 0u;
