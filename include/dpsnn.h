@@ -50,7 +50,11 @@ extern "C" {
 /* Current summation modes (the paper fixes no order or precision for the
  * sum of currents arriving in one step; Sec. 2, "Projection of synapses"). */
 #define DPSNN_SUM_ORDERED 0u  /* fp32 left fold: thalamic picks, stimulus list,
-                                 then deliveries by (delay, source id, synapse j) */
+                                 then deliveries by (delay, source id, synapse j);
+                                 a reference mode: each step also writes every
+                                 event's key and sorts them per target, several
+                                 times slower than FIXED at paper rates and far
+                                 slower when every input arrives every step */
 #define DPSNN_SUM_ATOMIC  1u  /* fp32, unordered atomics: not bit-reproducible
                                  (a source column's contributions to one target
                                  are summed exactly, then rounded to fp32 once
