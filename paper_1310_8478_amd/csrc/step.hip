@@ -823,8 +823,53 @@ __global__ __launch_bounds__(256) void k_deliver_seq(const NetDesc* __restrict__
 // One thread per neuron; each wavefront covers one 64-neuron raster word.
 // ---------------------------------------------------------------------------
 // Events per target up to which the ordered fold selects keys one by one
-// (O(n^2) reads, no writes); above it the target's events are sorted first.
+// (O(n^2) reads, no writes); above it the target's events are sorted first:
+// by the whole wavefront in LDS up to kLdsSort events (and folded there),
+// else in place by the target's own thread.
 constexpr uint32_t kSelectFold = 32;
+constexpr uint32_t kLdsSort = 1024;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One target's n (kSelectFold < n <= kLdsSort) events sorted by key by all 64
+// lanes of a wavefront in the wavefront's LDS arrays sk / sw: loaded padded
+// to a power of two with keys above every real key, then a bitonic network.
+// Called with the whole wavefront active; the sorted events stay in LDS.
+__device__ __forceinline__ void wave_sort_events(const unsigned long long* __restrict__ key,
+                                                 const float* __restrict__ wt, uint32_t n,
+                                                 unsigned long long* __restrict__ sk,
+                                                 float* __restrict__ sw) {
+    const uint32_t lane = lane_id();
+    uint32_t P = 64u;
+    while (P < n) P <<= 1;
+    for (uint32_t x = lane; x < P; x += 64u) {
+        sk[x] = x < n ? key[x] : ~0ull;
+        sw[x] = x < n ? wt[x] : 0.0f;
+    }
+    wave_sync();
+    for (uint32_t k = 2u; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0u; j >>= 1) {
+            for (uint32_t x = lane; x < P; x += 64u) {
+                const uint32_t y = x ^ j;
+                if (y > x) {
+                    const unsigned long long a = sk[x], b = sk[y];
+                    if ((a > b) == ((x & k) == 0u)) {
+                        sk[x] = b;
+                        sk[y] = a;
+                        const float wa = sw[x];
+                        sw[x] = sw[y];
+                        sw[y] = wa;
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+}
 
 // One target's n events of a step, sorted in place by key (weights move
 // with their keys): heapsort, O(n log n) in the target's own slot range.
@@ -934,6 +979,35 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
         }
     }
     __syncthreads();
+    // ORDERED: targets with many events this step are sorted by the whole
+    // wavefront in LDS, and each such target's lane folds them there, after
+    // its external input (the same sums as the per-neuron path below)
+    float lds_fold = 0.0f;
+    if constexpr (MODE == DPSNN_SUM_ORDERED) {
+        __shared__ unsigned long long ssk[4][kLdsSort];
+        __shared__ float ssw[4][kLdsSort];
+        const uint32_t kk = valid ? c * d.Ncol + l : 0u;
+        const uint32_t ne = valid ? ev_cnt[kk] : 0u;
+        const uint32_t b0 = valid ? ev_start[kk] : 0u;
+        const bool mine = valid && ne > kSelectFold && ne <= kLdsSort;
+        if (mine) {
+            const uint32_t hits = thc[wv][lane];
+            for (uint32_t h = 0; h < hits; ++h) lds_fold = lds_fold + thal_mv;
+            for (uint32_t e = sb; e < se; ++e)
+                if (stim_id[e] == kk) lds_fold = lds_fold + stim_mv[e];
+        }
+        unsigned long long big = __ballot(mine);
+        while (big) {
+            const uint32_t src = (uint32_t)__ffsll((long long)big) - 1u;
+            big &= big - 1ull;
+            const uint32_t nb = __shfl(ne, (int)src, 64);
+            const uint32_t bb = __shfl(b0, (int)src, 64);
+            wave_sort_events(ev_key + bb, ev_w + bb, nb, ssk[wv], ssw[wv]);
+            if (lane == src)
+                for (uint32_t x = 0; x < nb; ++x) lds_fold = lds_fold + ssw[wv][x];
+            wave_sync();  // the next target reuses the LDS arrays
+        }
+    }
     if (valid) {
         const uint32_t k = c * d.Ncol + l;
         // external input: this neuron's thalamic hits, then the stimulus
@@ -969,6 +1043,8 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
                     a32 = a32 + bw;
                     prev = best;
                 }
+            } else if (ne <= kLdsSort) {
+                a32 = lds_fold;  // folded from LDS above, external input first
             } else {
                 sort_events(ev_key + b0, ev_w + b0, ne);
                 for (uint32_t x = 0; x < ne; ++x) a32 = a32 + ev_w[b0 + x];
