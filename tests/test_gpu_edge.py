@@ -3,7 +3,8 @@ reproducible summation modes: the smallest column and fan-out, a network
 without inhibitory neurons, a silent network (no thalamic input) with and
 without stimulus, no consolidation, the longest delay, all targets in the
 own column or none, a fan-out larger than the column, ragged raster words,
-and the widest column (1024 raster words per column, one delay per chunk)."""
+the widest column (1024 raster words per column, one delay per chunk), and a
+saturated column whose targets receive more than 1024 events per step."""
 import numpy as np
 import pytest
 
@@ -55,6 +56,11 @@ EDGE = {
     "widest_column": (W.make_config(grid_x=1, grid_y=1, neurons_per_column=65535,
                                     synapses_per_neuron=3, thalamic_rate=300.0, w_exc_init=10.0,
                                     weight_update_period=40), 120),
+    # every neuron fires in every step from step ~20 on and each target then
+    # receives 1200-1600 events per step (above the ORDERED fold's LDS sort)
+    "saturated_fanout": (W.make_config(grid_x=1, grid_y=1, neurons_per_column=300,
+                                       synapses_per_neuron=1500, w_exc_init=10.0, w_inh=-0.5,
+                                       w_max=10.0, thalamic_rate=20.0, weight_update_period=60), 120),
 }
 
 
@@ -69,6 +75,9 @@ def test_edge_configuration_bitexact(dp, orc, name, mode):
     assert_bitexact(g, o)
     if name != "widest_column":
         assert len(o["tt"]) > 0, "the case should be active"
+    if name == "saturated_fanout":
+        per = np.bincount(o["tt"], minlength=T + 1)
+        assert (per[40:] == cfg["neurons_per_column"]).sum() >= 60, "the column must saturate"
 
 
 @pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
