@@ -198,3 +198,46 @@ def test_tables_match_test_side_tables(orc):
         if k >= 1:
             assert np.float32(orc.tm(cfg, k)) == tm[k]
     assert tp[2000] == 0 and tp[1000] > 0
+
+
+def _golden_consolidation():
+    out = []
+    for line in open(os.path.join(GOLD, "consolidation_hand.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        head, before, after = line.split("|")
+        name, beta, gamma, w0, wmax, posts = head.split()
+        out.append(dict(name=name, beta=float(beta), gamma=float(gamma), w0=float(w0),
+                        wmax=float(wmax), posts=[int(x) for x in posts.split(",")],
+                        before=[int(x, 16) for x in before.split()],
+                        after=[int(x, 16) for x in after.split()]))
+    return out
+
+
+@pytest.mark.parametrize("case", _golden_consolidation(), ids=lambda c: c["name"])
+def test_consolidation_hand_values(orc, case):
+    # the hand-traced pair (pre stamped 10, delay 5, posts forced) followed by
+    # one consolidation after step 19; P, D before it and w, P, D after it
+    # against values worked by hand (bias sign, decay, both clamps, D reset,
+    # the sign of a zero)
+    cfg = W.make_config(grid_x=1, grid_y=1, neurons_per_column=20, synapses_per_neuron=4,
+                        w_exc_init=case["w0"], w_max=case["wmax"], thalamic_rate=0.0,
+                        weight_update_period=20, wu_bias=case["beta"], sd_decay=case["gamma"])
+    i, j, k = _find_synapse(orc, cfg, 5)
+    stim_t = [9] + [p - 1 for p in case["posts"]]
+    stim_id = [i] + [k] * len(case["posts"])
+    for T, want in ((19, case["before"][:2] + [None]), (20, case["after"][1:] + [case["after"][0]])):
+        net = orc.Net(cfg, T)
+        net.set_stimulus(stim_t, stim_id, [200.0] * len(stim_t))
+        net.run(T)
+        tt, ii = net.raster()
+        assert sorted(zip(tt.tolist(), ii.tolist())) == sorted(
+            [(10, i)] + [(p, k) for p in case["posts"]]), "only the forced spikes may occur"
+        syn = net.synapses(i * 4 + j, 1)
+        net.close()
+        P, D, w = (int(syn[x].view(np.uint32)[0]) for x in ("P", "D", "w"))
+        assert (P, D) == tuple(want[:2]), (hex(P), hex(D))
+        if want[2] is not None:
+            assert w == want[2], hex(w)
+        else:
+            assert w == int(np.float32(case["w0"]).view(np.uint32))

@@ -135,3 +135,28 @@ def test_threshold_is_inclusive(orc):
     below = np.nextafter(hit, np.float32(-np.inf))
     if _v_after_step(v0, u0, below, a, b) < np.float32(30.0):
         assert not orc.neuron_step(float(v0), float(u0), float(below), a, b, c, d)[2]
+
+
+def _golden_neuron_steps():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "neuron_step_hand.txt")
+    out = []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        left, right = line.split("|")
+        kind, v, u, I = left.split()
+        vb, ub, fired = right.split()
+        out.append((kind, float(v), float(u), float(I), int(vb, 16), int(ub, 16), int(fired)))
+    return out
+
+
+@pytest.mark.parametrize("kind,v,u,I,vbits,ubits,fired", _golden_neuron_steps())
+def test_one_step_hand_values(orc, kind, v, u, I, vbits, ubits, fired):
+    # one step from a stated state against values worked by hand in binary32
+    # (two 0.5 ms sub-steps of v, then u with the new v, then the reset)
+    prm = RS if kind == "RS" else FS
+    v1, u1, f = orc.neuron_step(np.float32(v), np.float32(u), np.float32(I), *prm)
+    assert int(np.float32(v1).view(np.uint32)) == vbits
+    assert int(np.float32(u1).view(np.uint32)) == ubits
+    assert int(f) == fired
