@@ -46,6 +46,7 @@ extern "C" {
 #define DPSNN_E_RANGE  (-4)   /* requested steps are not (or no longer) held */
 #define DPSNN_E_BUFSZ  (-5)   /* caller buffer too small; *n_out holds the size needed */
 #define DPSNN_E_TIMEOUT (-6)  /* a wait ended before the job finished */
+#define DPSNN_E_CANCELED (-7) /* the job was cancelled (dpsnn_server_cancel) */
 
 /* Current summation modes (the paper fixes no order or precision for the
  * sum of currents arriving in one step; Sec. 2, "Projection of synapses"). */
@@ -123,7 +124,13 @@ typedef struct dpsnn_net dpsnn_net;
 int dpsnn_default_config(dpsnn_config *cfg);
 
 /* Device bytes that dpsnn_build_network would allocate for *cfg, without
- * allocating.  DPSNN_E_INVAL if *cfg is invalid. */
+ * allocating: the network arrays of the construction phase (Sec. 2, "Initial
+ * construction of the connectivity infrastructure": forward synapse lists of
+ * every neuron, the incoming-synapse index, neuron state), the STDP tables,
+ * the network's launch tables, and the bounded scratch of one read-back
+ * (dpsnn_read_weights / dpsnn_read_connectivity).  A checkpoint save or load
+ * takes a further transient buffer (see dpsnn_save).  DPSNN_E_INVAL if *cfg
+ * is invalid. */
 int dpsnn_footprint_bytes(const dpsnn_config *cfg, uint64_t *bytes);
 
 /* Generate the network on the device (Sec. 2, "Initial construction of the
@@ -148,27 +155,43 @@ int dpsnn_build_network(const dpsnn_config *cfg, const dpsnn_device *dev, dpsnn_
  * directly.  The results are the same either way. */
 int dpsnn_step(dpsnn_net *net, uint32_t n_steps);
 
-/* Wait for all enqueued work of the network. */
+/* Wait for all enqueued work of the network: every step enqueued so far has
+ * completed (the end of the paper's per-step loop, Sec. 2, items 2.1-2.7). */
 int dpsnn_sync(dpsnn_net *net);
 
 /* Steps completed so far (the next step index). */
 int dpsnn_time(dpsnn_net *net, uint32_t *t);
 
-/* Spikes with stamp in [t_begin, t_end), sorted by (stamp, id), written to
- * times[] and ids[] (each of capacity cap).  *n_out receives the number of
- * spikes.  DPSNN_E_RANGE if the range reaches past the last step or before
- * the retained raster window; DPSNN_E_BUFSZ if cap is too small. */
+/* The spike list observable (Sec. 2, "Production of observables": times and
+ * ids of the spikes): spikes with stamp in [t_begin, t_end), sorted by
+ * (stamp, id), written to times[] and ids[] (each of capacity cap).  *n_out
+ * receives the number of spikes.  DPSNN_E_RANGE if the range reaches past
+ * the last step or before the retained raster window; DPSNN_E_BUFSZ if cap
+ * is too small (*n_out then holds the count needed).  No device memory is
+ * allocated. */
 int dpsnn_read_spikes(dpsnn_net *net, uint32_t t_begin, uint32_t t_end,
                       uint32_t *times, uint32_t *ids, size_t cap, size_t *n_out);
 
-/* Synaptic state of canonical synapses [first, first + count): weight w,
+/* The synaptic-value observable (Sec. 2, "Production of observables"; STDP
+ * rule of Sec. 2): for canonical synapses [first, first + count), weight w,
  * potentiation accumulator P and depression accumulator D (the synaptic
- * derivative is P - D).  Any output pointer may be NULL. */
+ * derivative is P - D), written to the caller's host arrays in canonical
+ * order.  Any output pointer may be NULL.  DPSNN_E_RANGE if the range passes
+ * the last synapse.  The call allocates one transient device scratch through
+ * the network's allocator (the dpsnn_device callbacks, else hipMalloc) and
+ * frees it before returning: staging of at most 8 MiB and, when P is asked
+ * for, P of whole source columns (at most 32 MiB, at least one column's
+ * neurons_per_column x synapses_per_neuron floats); it scales with the
+ * columns the range spans, not with the network.  DPSNN_E_NOMEM if that
+ * allocation fails. */
 int dpsnn_read_weights(dpsnn_net *net, uint64_t first, uint64_t count,
                        float *w, float *P, float *D);
 
-/* Connectivity of canonical synapses [first, first + count): global target
- * id and delay in ms.  Either pointer may be NULL. */
+/* The connectivity observable (Sec. 2, "Projection of synapses": each
+ * synapse's target and axonal delay) of canonical synapses [first, first +
+ * count): global target id and delay in ms, in canonical order.  Either
+ * pointer may be NULL.  Transient staging of at most 8 MiB through the
+ * network's allocator, as dpsnn_read_weights. */
 int dpsnn_read_connectivity(dpsnn_net *net, uint64_t first, uint64_t count,
                             uint32_t *target, uint8_t *delay);
 
@@ -176,6 +199,10 @@ int dpsnn_read_connectivity(dpsnn_net *net, uint64_t first, uint64_t count,
  * observables); arrays of length grid_x*grid_y*neurons_per_column. */
 int dpsnn_read_state(dpsnn_net *net, float *v, float *u);
 
+/* Counters and per-block timers (Sec. 3, Table 2's per-block profiling;
+ * "Production of observables" for the spike count): steps, spikes, delivered
+ * events, LTP visits, consolidations, and the per-kernel device time
+ * accumulated while dpsnn_set_timing is on.  Synchronises the stream. */
 int dpsnn_get_stats(dpsnn_net *net, dpsnn_stats *stats);
 
 /* External stimulus (test hook): entry e adds mv[e] to the input current of
@@ -184,15 +211,34 @@ int dpsnn_get_stats(dpsnn_net *net, dpsnn_stats *stats);
 int dpsnn_set_stimulus(dpsnn_net *net, const uint32_t *t, const uint32_t *id,
                        const float *mv, size_t n);
 
+/* State probes (Sec. 2, "Production of observables": the trace of the
+ * membrane potential and other state variables of individual neurons can be
+ * activated).  After every later step the library records v and u of the
+ * `count` neurons ids[0..count) on the device (a ring of raster_steps rows).
+ * Replaces any previous probe set; count = 0 removes it.  At most 65536
+ * probes; DPSNN_E_INVAL for an id out of range or a network in a batch.
+ * The probe buffers (2 x count x raster_steps floats) come from the
+ * network's allocator. */
+int dpsnn_set_probes(dpsnn_net *net, const uint32_t *ids, uint32_t count);
+/* Probed state after steps s in [t_begin, t_end) (s = number of steps
+ * completed, as spike stamps): v[(s - t_begin) * count + p] and likewise u,
+ * for probe p in the order given to dpsnn_set_probes.  Either pointer may be
+ * NULL.  DPSNN_E_RANGE for steps not recorded (before the probes were set,
+ * past the last step, or older than raster_steps). */
+int dpsnn_read_probes(dpsnn_net *net, uint32_t t_begin, uint32_t t_end, float *v, float *u);
+
 /* Per-kernel device timers (Table 2's per-block profiling): when enabled,
  * every kernel launch of dpsnn_step is bracketed by events and its duration
  * accumulated into dpsnn_stats at the next dpsnn_get_stats. */
 int dpsnn_set_timing(dpsnn_net *net, int enable);
 
 /* Launch-shape knobs (results never depend on them).  "Automatic" values
- * (the defaults) follow the measured regime of the launch: a launch over at
- * least 2048 columns whose source columns deliver fewer events per step than
- * their current window has entries is sparse, every other launch dense.
+ * (the defaults) follow the measured regime of the launch: a launch is
+ * sparse when its source columns deliver fewer events per step than their
+ * current window has entries (with hysteresis: sparse below 0.8 of that,
+ * dense above it) and it has enough work to fill the GPU with small
+ * workgroups: at least 2048 columns, or at least 64 columns whose column
+ * parts (key 5) give at least 512 workgroups; every other launch is dense.
  *   key 0: delivery workgroup size 256, 512, 1024; 0 = automatic (256 / 1024)
  *   key 1: LTP workgroup size 256, 512, 1024; 0 = automatic (256 / 1024)
  *   key 2: LDS current window in delivery: 1 = over all 13 reachable
@@ -248,7 +294,11 @@ int dpsnn_get_config(dpsnn_net *net, dpsnn_config *cfg);
 /* Bytes dpsnn_save writes for this network. */
 int dpsnn_checkpoint_bytes(dpsnn_net *net, uint64_t *bytes);
 /* Write the checkpoint into the caller's host buffer buf of cap bytes
- * (DPSNN_E_BUFSZ if too small); waits for the network's stream. */
+ * (DPSNN_E_BUFSZ if too small); waits for the network's stream.  P moves to
+ * the forward layout through a transient device buffer from the network's
+ * allocator: at most 1 GiB (all columns when they fit), halved on allocation
+ * failure down to one column; DPSNN_E_NOMEM if even that fails.  dpsnn_load
+ * takes the same buffer. */
 int dpsnn_save(dpsnn_net *net, void *buf, uint64_t cap);
 /* Build a network on *dev from a checkpoint of `size` bytes (as written by
  * dpsnn_save) and restore its state; DPSNN_E_INVAL if buf is not a whole,
@@ -352,12 +402,22 @@ int dpsnn_server_submit(dpsnn_server *srv, const dpsnn_config *cfg, uint32_t ste
 /* Current state of a job; DPSNN_E_INVAL for an unknown or released id. */
 int dpsnn_server_query(dpsnn_server *srv, uint64_t job, dpsnn_job_info *info);
 /* Block until the job is DONE or FAILED (timeout_s < 0: no limit), then
- * fill *info.  DPSNN_E_TIMEOUT (with *info filled) if the time ran out. */
+ * fill *info.  DPSNN_E_TIMEOUT (with *info filled) if the time ran out.  A
+ * job this call returns as DONE or FAILED counts as collected:
+ * dpsnn_server_wait_any does not return it. */
 int dpsnn_server_wait(dpsnn_server *srv, uint64_t job, double timeout_s, dpsnn_job_info *info);
-/* Block until some job finishes that no earlier dpsnn_server_wait_any call
- * returned; jobs are returned in the order they finished.
- * DPSNN_E_TIMEOUT if none finished in time. */
+/* Block until some job finishes that no earlier dpsnn_server_wait_any or
+ * dpsnn_server_wait call returned; jobs are returned in the order they
+ * finished.  DPSNN_E_TIMEOUT if none finished in time. */
 int dpsnn_server_wait_any(dpsnn_server *srv, double timeout_s, dpsnn_job_info *info);
+/* Cancel a QUEUED or RUNNING job; returns at once.  A queued job becomes
+ * FAILED (error DPSNN_E_CANCELED) immediately; a job being built or stepped
+ * becomes FAILED (DPSNN_E_CANCELED) once no launched work uses its network:
+ * after its build, or after the quantum in flight at the call (it may
+ * advance by that quantum).  The other jobs' results are unchanged.  Its
+ * network and footprint are then freed by dpsnn_server_release, as for any
+ * finished job.  DPSNN_E_INVAL for an unknown, released or finished job. */
+int dpsnn_server_cancel(dpsnn_server *srv, uint64_t job);
 /* Free a DONE or FAILED job's network and return its footprint to the
  * budget.  DPSNN_E_INVAL if the job is still queued or running, or if its
  * network belongs to a batch. */

@@ -385,7 +385,11 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
                                  hipMemcpyHostToDevice, stream));
     }
     L.host_descs.resize(cnt);
-    for (uint32_t k = 0; k < cnt; ++k) L.host_descs[k] = m[k]->make_desc();
+    L.max_probes = 0;
+    for (uint32_t k = 0; k < cnt; ++k) {
+        L.host_descs[k] = m[k]->make_desc();
+        L.max_probes = std::max(L.max_probes, m[k]->probe_n);
+    }
     DPSNN_HIP(hipMemcpyAsync(L.descs, L.host_descs.data(), sizeof(NetDesc) * cnt, hipMemcpyHostToDevice, stream));
     if (sync) DPSNN_HIP(hipStreamSynchronize(stream));
     return DPSNN_OK;
@@ -396,7 +400,11 @@ int make_launch_set(LaunchSet& L, Net* const* m, uint32_t cnt, const dpsnn_devic
 namespace {
 
 int refresh_descs(LaunchSet& L, Net* const* m, hipStream_t stream) {
-    for (uint32_t k = 0; k < L.K; ++k) L.host_descs[k] = m[k]->make_desc();
+    L.max_probes = 0;
+    for (uint32_t k = 0; k < L.K; ++k) {
+        L.host_descs[k] = m[k]->make_desc();
+        L.max_probes = std::max(L.max_probes, m[k]->probe_n);
+    }
     DPSNN_HIP(hipMemcpyAsync(L.descs, L.host_descs.data(), sizeof(NetDesc) * L.K, hipMemcpyHostToDevice, stream));
     DPSNN_HIP(hipStreamSynchronize(stream));
     return DPSNN_OK;
@@ -531,6 +539,7 @@ NetDesc Net::make_desc() const {
     nd.sd_decay = cfg.sd_decay; nd.w_max = cfg.w_max; nd.S_exc = S_exc;
     nd.ev_cnt = ev_cnt; nd.ev_start = ev_start; nd.ev_key = ev_key; nd.ev_w = ev_w;
     nd.cursor = cursor;
+    nd.probe_id = probe_id; nd.probe_buf = probe_buf; nd.probe_n = probe_n;
     return nd;
 }
 
@@ -571,7 +580,9 @@ size_t pad16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // Byte sizes of the checkpoint arrays, in file order; the raster ring is
 // entry kCkptRing.
+constexpr uint32_t kMaxProbes = 1u << 16;  // state probes of one network
 constexpr size_t kCkptRing = 4;
+constexpr size_t kCkptP = 8;   // P, stored in the forward layout
 
 std::vector<size_t> ckpt_sizes(uint64_t N, uint64_t C, uint64_t W, uint64_t R, uint64_t S,
                                uint64_t stim_n) {
@@ -617,6 +628,102 @@ bool ckpt_raster_in_range(const unsigned char* buf, const std::vector<size_t>& s
     return true;
 }
 
+// Device scratch of a read-back: P of whole source columns in the forward
+// layout (groups of columns, so a read of a few rows touches one column), and
+// staging for the requested outputs.  Bounded independently of the network
+// size; allocated through the network's allocator (callbacks or hipMalloc)
+// for the call and freed before it returns.
+constexpr size_t kReadPBytes = 32ull << 20;      // P of at least one whole column
+constexpr size_t kReadStageBytes = 8ull << 20;   // staging, at least one row
+
+size_t pad256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct ReadPlan {
+    uint32_t i0 = 0, i1 = 0, cA = 0, cB = 0;
+    uint32_t group = 1;        // source columns per P group
+    uint32_t stage_rows = 1;   // rows per staging chunk
+    size_t per_syn = 0;        // staged bytes per synapse
+    size_t pg_bytes = 0, stage_bytes = 0;
+    size_t bytes() const { return pg_bytes + stage_bytes; }
+};
+
+size_t stage_bytes_for(uint32_t rows, uint32_t M, bool tgt, bool dly, bool w, bool P, bool D) {
+    const size_t m = (size_t)rows * M;
+    return (tgt ? pad256(4 * m) : 0) + (dly ? pad256(m) : 0) + (w ? pad256(4 * m) : 0) +
+           (P ? pad256(4 * m) : 0) + (D ? pad256(4 * m) : 0);
+}
+
+// The scratch layout of a read of canonical synapses [first, first + count)
+// within `limit` bytes; false if not even one column and one row fit.
+bool plan_read(const Net& n, uint64_t first, uint64_t count, bool tgt, bool dly, bool w,
+                      bool P, bool D, size_t p_budget, size_t stage_budget, size_t limit,
+                      ReadPlan& pl) {
+    const uint32_t M = n.d.M, Ncol = n.d.Ncol;
+    const uint64_t colb = 4ull * Ncol * M;
+    pl.i0 = (uint32_t)(first / M);
+    pl.i1 = (uint32_t)((first + count + M - 1) / M);
+    pl.cA = pl.i0 / Ncol;
+    pl.cB = (pl.i1 - 1) / Ncol + 1;
+    pl.per_syn = (tgt ? 4 : 0) + (dly ? 1 : 0) + (w ? 4 : 0) + (P ? 4 : 0) + (D ? 4 : 0);
+    const uint32_t rows = pl.i1 - pl.i0;
+    pl.stage_rows = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(rows, stage_budget / std::max<size_t>(1, (size_t)M * pl.per_syn)));
+    pl.group = P ? (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(pl.cB - pl.cA, p_budget / colb))
+                 : pl.cB - pl.cA;
+    for (;;) {
+        pl.pg_bytes = P ? pad256((size_t)pl.group * colb) : 0;
+        pl.stage_bytes = stage_bytes_for(pl.stage_rows, M, tgt, dly, w, P, D);
+        if (pl.bytes() <= limit) return true;
+        if (P && pl.group > 1) pl.group = (pl.group + 1) / 2;
+        else if (pl.stage_rows > 1) pl.stage_rows = (pl.stage_rows + 1) / 2;
+        else return false;
+    }
+}
+
+// Scratch bytes a read of the whole network may take (counted in the
+// footprint, so that reads of a served job stay inside its reservation).
+uint64_t read_reserve_bytes(uint64_t C, uint64_t Ncol, uint64_t M) {
+    const uint64_t colb = 4ull * Ncol * M;
+    const uint64_t group = std::max<uint64_t>(1, std::min<uint64_t>(C, kReadPBytes / colb));
+    const uint64_t rows = std::max<uint64_t>(1, std::min<uint64_t>(C * Ncol, kReadStageBytes / (17ull * M)));
+    return pad256(group * colb) + 4 * pad256(4 * rows * M) + pad256(rows * M);
+}
+
+// Save and load move P between the reverse order and the forward layout in
+// groups of whole source columns through a transient device buffer from the
+// network's allocator: all columns at once if kCkptPBytes allows, else the
+// largest group the allocator grants, halving down to one column.
+constexpr uint64_t kCkptPBytes = 1ull << 30;
+
+struct PGroups {
+    Net* n = nullptr;
+    float* buf = nullptr;
+    size_t bytes = 0;
+    uint32_t group = 0;   // source columns per group
+    ~PGroups() {
+        if (buf) {
+            (void)hipStreamSynchronize(n->stream);
+            dfree(*n, buf, bytes);
+        }
+    }
+};
+
+bool alloc_pgroups(Net* n, PGroups& g) {
+    g.n = n;
+    const uint64_t colb = 4ull * n->d.Ncol * n->d.M;
+    uint64_t want = std::max<uint64_t>(1, std::min<uint64_t>(n->d.C, kCkptPBytes / colb));
+    for (;;) {
+        g.bytes = std::max<size_t>((size_t)(want * colb), 256);
+        g.buf = static_cast<float*>(dev_alloc(n->dev, n->stream, g.bytes, nullptr));
+        if (g.buf) {
+            g.group = (uint32_t)want;
+            return true;
+        }
+        if (want == 1) return false;
+        want = (want + 1) / 2;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -659,8 +766,17 @@ int dpsnn_footprint_bytes(const dpsnn_config* cfg, uint64_t* bytes) {
     if (!bytes) return fail(DPSNN_E_INVAL, "bytes is NULL");
     uint64_t tot = 0;
     for (size_t b : array_bytes(cfg, d)) tot += std::max<size_t>(b, 256);
-    // tables (at most a few hundred KB)
-    tot += 2 * 4 * 65536;
+    // STDP amplitude tables, as long as the build makes them
+    tot += std::max<size_t>(4 * std::max<size_t>(amplitude_table(cfg->a_plus, cfg->tau_plus).size(), 1), 256);
+    tot += std::max<size_t>(4 * std::max<size_t>(amplitude_table(cfg->a_minus, cfg->tau_minus).size(), 1), 256);
+    // the network's own launch tables: event counter, descriptor, block maps
+    // of columns and raster words, consolidation chunks (at most one per
+    // 256 * kWupdateItems reverse entries of a column, plus one per column)
+    const uint64_t wu_chunks = d.S_exc / (256ull * kWupdateItems) + d.C;
+    tot += 256 + std::max<uint64_t>(sizeof(NetDesc), 256) + std::max<uint64_t>(8ull * d.C, 256) +
+           std::max<uint64_t>(8ull * ((d.C * d.W + 3) / 4), 256) + std::max<uint64_t>(8ull * wu_chunks, 256);
+    // the scratch of a read-back (dpsnn_read_weights, dpsnn_read_connectivity)
+    tot += read_reserve_bytes(d.C, d.Ncol, d.M);
     *bytes = tot;
     return DPSNN_OK;
 }
@@ -885,67 +1001,64 @@ int dpsnn_read_spikes(dpsnn_net* h, uint32_t t_begin, uint32_t t_end, uint32_t* 
     return DPSNN_OK;
 }
 
+// Reads canonical synapses [first, first + count) in groups of whole source
+// columns: P of a group is moved from the reverse order into the forward
+// layout of the scratch, then the rows are staged and copied to the caller's
+// host arrays.  ws / ws_bytes: a caller-provided device region (no
+// allocation), or null to allocate through the network's allocator.
 static int read_rows_common(Net* n, uint64_t first, uint64_t count, uint32_t* tgt, uint8_t* dly,
-                            float* w, float* P, float* D) {
+                            float* w, float* P, float* D, void* ws = nullptr, size_t ws_bytes = 0) {
     if (first > n->S || count > n->S - first) return fail(DPSNN_E_RANGE, "synapse range out of bounds");
     if (count == 0) return DPSNN_OK;
     DPSNN_HIP(hipSetDevice(n->dev.device));
-    const uint32_t M = n->d.M;
-    const uint32_t i0 = (uint32_t)(first / M);
-    const uint32_t i1 = (uint32_t)((first + count + M - 1) / M);
-    float* Pf = nullptr;
-    std::vector<void*> tmp;
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(n->stream);
-        for (void* q : tmp) (void)hipFree(q);
-    };
-    if (P) {
-        if (hipMalloc((void**)&Pf, sizeof(float) * n->S) != hipSuccess) return fail(DPSNN_E_NOMEM, "temporary P buffer");
-        tmp.push_back(Pf);
-        hipError_t e = launch_scatter_P(*n, Pf);
-        if (e != hipSuccess) { cleanup(); return fail(DPSNN_E_DEVICE, hipGetErrorString(e)); }
+    const uint32_t M = n->d.M, Ncol = n->d.Ncol;
+    const uint64_t colsz = (uint64_t)Ncol * M;
+    ReadPlan pl;
+    const size_t limit = ws ? ws_bytes : ~(size_t)0;
+    if (!plan_read(*n, first, count, tgt, dly, w, P, D, kReadPBytes, kReadStageBytes, limit, pl))
+        return fail(DPSNN_E_INVAL, "one column of this network does not fit the read workspace");
+    unsigned char* base = static_cast<unsigned char*>(ws);
+    const size_t nbytes = std::max<size_t>(pl.bytes(), 256);
+    if (!base) {
+        base = static_cast<unsigned char*>(dev_alloc(n->dev, n->stream, nbytes, nullptr));
+        if (!base) return fail(DPSNN_E_NOMEM, "read scratch of " + std::to_string(nbytes) + " bytes");
     }
-    const uint32_t chunk_rows = std::max<uint32_t>(1, (uint32_t)((16ull << 20) / M));
-    const uint32_t crow = std::min<uint32_t>(chunk_rows, i1 - i0);
-    const size_t cs = (size_t)crow * M;
+    auto done = [&](int rc) {
+        (void)hipStreamSynchronize(n->stream);
+        if (base && !ws) dfree(*n, base, nbytes);
+        return rc;
+    };
+    float* Pg = P ? reinterpret_cast<float*>(base) : nullptr;
+    unsigned char* st = base + pl.pg_bytes;
+    const size_t sm = (size_t)pl.stage_rows * M;
     uint32_t* d_tgt = nullptr; uint8_t* d_dly = nullptr; float *d_w = nullptr, *d_P = nullptr, *d_D = nullptr;
-    bool ok = true;
-    if (tgt) { ok &= hipMalloc((void**)&d_tgt, cs * 4) == hipSuccess; if (d_tgt) tmp.push_back(d_tgt); }
-    if (dly) { ok &= hipMalloc((void**)&d_dly, cs) == hipSuccess; if (d_dly) tmp.push_back(d_dly); }
-    if (w) { ok &= hipMalloc((void**)&d_w, cs * 4) == hipSuccess; if (d_w) tmp.push_back(d_w); }
-    if (P) { ok &= hipMalloc((void**)&d_P, cs * 4) == hipSuccess; if (d_P) tmp.push_back(d_P); }
-    if (D) { ok &= hipMalloc((void**)&d_D, cs * 4) == hipSuccess; if (d_D) tmp.push_back(d_D); }
-    if (!ok) { cleanup(); return fail(DPSNN_E_NOMEM, "temporary read buffers"); }
-    std::vector<uint32_t> h_tgt(tgt ? cs : 0);
-    std::vector<uint8_t> h_dly(dly ? cs : 0);
-    std::vector<float> h_w(w ? cs : 0), h_P(P ? cs : 0), h_D(D ? cs : 0);
-    for (uint32_t r0 = i0; r0 < i1; r0 += crow) {
-        const uint32_t r1 = std::min<uint32_t>(i1, r0 + crow);
-        hipError_t e = launch_read_rows(*n, r0, r1, Pf, d_tgt, d_dly, d_w, d_P, d_D);
-        if (e != hipSuccess) { cleanup(); return fail(DPSNN_E_DEVICE, hipGetErrorString(e)); }
-        const size_t m = (size_t)(r1 - r0) * M;
-        e = hipStreamSynchronize(n->stream);
-        if (e == hipSuccess && tgt) e = hipMemcpy(h_tgt.data(), d_tgt, m * 4, hipMemcpyDeviceToHost);
-        if (e == hipSuccess && dly) e = hipMemcpy(h_dly.data(), d_dly, m, hipMemcpyDeviceToHost);
-        if (e == hipSuccess && w) e = hipMemcpy(h_w.data(), d_w, m * 4, hipMemcpyDeviceToHost);
-        if (e == hipSuccess && P) e = hipMemcpy(h_P.data(), d_P, m * 4, hipMemcpyDeviceToHost);
-        if (e == hipSuccess && D) e = hipMemcpy(h_D.data(), d_D, m * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) { cleanup(); return fail(DPSNN_E_DEVICE, hipGetErrorString(e)); }
-        // canonical indices covered by this chunk, clipped to the request
-        const uint64_t g0 = std::max<uint64_t>((uint64_t)r0 * M, first);
-        const uint64_t g1 = std::min<uint64_t>((uint64_t)r1 * M, first + count);
-        for (uint64_t g = g0; g < g1; ++g) {
-            const size_t src = (size_t)(g - (uint64_t)r0 * M);
-            const size_t dst = (size_t)(g - first);
-            if (tgt) tgt[dst] = h_tgt[src];
-            if (dly) dly[dst] = h_dly[src];
-            if (w) w[dst] = h_w[src];
-            if (P) P[dst] = h_P[src];
-            if (D) D[dst] = h_D[src];
+    if (tgt) { d_tgt = reinterpret_cast<uint32_t*>(st); st += pad256(4 * sm); }
+    if (dly) { d_dly = st; st += pad256(sm); }
+    if (w) { d_w = reinterpret_cast<float*>(st); st += pad256(4 * sm); }
+    if (P) { d_P = reinterpret_cast<float*>(st); st += pad256(4 * sm); }
+    if (D) { d_D = reinterpret_cast<float*>(st); st += pad256(4 * sm); }
+    for (uint32_t c0 = pl.cA; c0 < pl.cB; c0 += pl.group) {
+        const uint32_t c1 = std::min<uint32_t>(pl.cB, c0 + pl.group);
+        hipError_t e = P ? launch_P_to_forward(*n, Pg, c0, c1, false) : hipSuccess;
+        if (e != hipSuccess) return done(fail(DPSNN_E_DEVICE, hipGetErrorString(e)));
+        const uint32_t r_lo = std::max<uint32_t>(pl.i0, c0 * Ncol);
+        const uint32_t r_hi = std::min<uint32_t>(pl.i1, c1 * Ncol);
+        for (uint32_t r0 = r_lo; r0 < r_hi; r0 += pl.stage_rows) {
+            const uint32_t r1 = std::min<uint32_t>(r_hi, r0 + pl.stage_rows);
+            const uint64_t g0 = std::max<uint64_t>((uint64_t)r0 * M, first);
+            const uint64_t g1 = std::min<uint64_t>((uint64_t)r1 * M, first + count);
+            e = launch_read_rows(*n, r0, r1, g0, g1, Pg, (uint64_t)c0 * colsz, d_tgt, d_dly, d_w, d_P, d_D);
+            if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+            const size_t m = (size_t)(g1 - g0), o = (size_t)(g0 - first);
+            if (e == hipSuccess && tgt) e = hipMemcpy(tgt + o, d_tgt, 4 * m, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && dly) e = hipMemcpy(dly + o, d_dly, m, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && w) e = hipMemcpy(w + o, d_w, 4 * m, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && P) e = hipMemcpy(P + o, d_P, 4 * m, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && D) e = hipMemcpy(D + o, d_D, 4 * m, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return done(fail(DPSNN_E_DEVICE, hipGetErrorString(e)));
         }
     }
-    cleanup();
-    return DPSNN_OK;
+    return done(DPSNN_OK);
 }
 
 int dpsnn_read_weights(dpsnn_net* h, uint64_t first, uint64_t count, float* w, float* P, float* D) {
@@ -1049,6 +1162,72 @@ int dpsnn_set_stimulus(dpsnn_net* h, const uint32_t* t, const uint32_t* id, cons
     return DPSNN_OK;
 }
 
+int dpsnn_set_probes(dpsnn_net* h, const uint32_t* ids, uint32_t count) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    if (count && !ids) return fail(DPSNN_E_INVAL, "NULL probe ids");
+    if (count > kMaxProbes) return fail(DPSNN_E_INVAL, "too many probes");
+    for (uint32_t e = 0; e < count; ++e)
+        if (ids[e] >= n->d.N) return fail(DPSNN_E_INVAL, "probe neuron id out of range");
+    if (n->in_batch) return fail(DPSNN_E_INVAL, "set probes before adding the network to a batch");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    DPSNN_HIP(hipStreamSynchronize(n->stream));
+    auto drop = [&](void* p) {
+        if (!p) return;
+        for (size_t a = 0; a < n->allocs.size(); ++a) {
+            if (n->allocs[a].p == p) {
+                dfree(*n, p, n->allocs[a].bytes);
+                n->allocs.erase(n->allocs.begin() + (long)a);
+                break;
+            }
+        }
+    };
+    drop(n->probe_id);
+    drop(n->probe_buf);
+    n->probe_id = nullptr;
+    n->probe_buf = nullptr;
+    n->probe_n = 0;
+    n->desc_dirty = true;
+    if (count == 0) return DPSNN_OK;
+    n->probe_id = (uint32_t*)dalloc(*n, sizeof(uint32_t) * count);
+    n->probe_buf = (float*)dalloc(*n, sizeof(float) * 2 * (size_t)count * n->d.R);
+    if (!n->probe_id || !n->probe_buf) {
+        drop(n->probe_id);
+        drop(n->probe_buf);
+        n->probe_id = nullptr;
+        n->probe_buf = nullptr;
+        return fail(DPSNN_E_NOMEM, "probe buffers");
+    }
+    DPSNN_HIP(hipMemcpy(n->probe_id, ids, sizeof(uint32_t) * count, hipMemcpyHostToDevice));
+    n->probe_n = count;
+    n->probe_from = n->t + 1;
+    return DPSNN_OK;
+}
+
+int dpsnn_read_probes(dpsnn_net* h, uint32_t t_begin, uint32_t t_end, float* v, float* u) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    if (t_end < t_begin) return fail(DPSNN_E_INVAL, "t_end < t_begin");
+    if (t_end == t_begin) return DPSNN_OK;
+    if (!n->probe_n) return fail(DPSNN_E_INVAL, "no probes are set");
+    const uint32_t now = n->t, R = n->d.R;
+    if (t_begin < n->probe_from || t_end > now + 1)
+        return fail(DPSNN_E_RANGE, "steps outside the recorded probe range");
+    if (now >= R && t_begin < now - R + 1)
+        return fail(DPSNN_E_RANGE, "steps before the retained probe window");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    DPSNN_HIP(hipStreamSynchronize(n->stream));
+    const size_t pn = n->probe_n;
+    std::vector<float> row(2 * pn);
+    for (uint32_t s = t_begin; s < t_end; ++s) {
+        DPSNN_HIP(hipMemcpy(row.data(), n->probe_buf + (size_t)(s % R) * 2 * pn, sizeof(float) * 2 * pn,
+                            hipMemcpyDeviceToHost));
+        if (v) std::memcpy(v + (size_t)(s - t_begin) * pn, row.data(), sizeof(float) * pn);
+        if (u) std::memcpy(u + (size_t)(s - t_begin) * pn, row.data() + pn, sizeof(float) * pn);
+    }
+    return DPSNN_OK;
+}
+
 int dpsnn_set_timing(dpsnn_net* h, int enable) {
     Net* n = reinterpret_cast<Net*>(h);
     if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
@@ -1111,18 +1290,28 @@ int dpsnn_save(dpsnn_net* h, void* buf, uint64_t cap) {
     hd.total_bytes = total;
     std::memset(out, 0, pad16(sizeof(hd)));
     std::memcpy(out, &hd, sizeof(hd));
-    float* Pf = nullptr;
-    if (hipMalloc((void**)&Pf, sizeof(float) * std::max<uint64_t>(n->S, 1)) != hipSuccess)
-        return fail(DPSNN_E_NOMEM, "temporary P buffer");
-    hipError_t e = launch_scatter_P(*n, Pf);
-    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    hipError_t e = hipSuccess;
     size_t off = pad16(sizeof(hd));
-    for (const CkptPart& q : parts) {
-        if (e == hipSuccess && q.bytes)
-            e = hipMemcpy(out + off, q.dev ? q.dev : (void*)Pf, q.bytes, hipMemcpyDeviceToHost);
+    size_t off_P = 0;
+    for (size_t k = 0; k < parts.size(); ++k) {
+        const CkptPart& q = parts[k];
+        if (k == kCkptP) off_P = off;
+        else if (e == hipSuccess && q.bytes) e = hipMemcpy(out + off, q.dev, q.bytes, hipMemcpyDeviceToHost);
         off += pad16(q.bytes);
     }
-    (void)hipFree(Pf);
+    if (e != hipSuccess) return fail(DPSNN_E_DEVICE, hipGetErrorString(e));
+    // P in the forward layout, a group of source columns at a time
+    PGroups pg;
+    if (!alloc_pgroups(n, pg)) return fail(DPSNN_E_NOMEM, "checkpoint P buffer (one column)");
+    const uint64_t colsz = (uint64_t)n->d.Ncol * n->d.M;
+    for (uint32_t c0 = 0; c0 < n->d.C && e == hipSuccess; c0 += pg.group) {
+        const uint32_t c1 = std::min<uint32_t>(n->d.C, c0 + pg.group);
+        e = launch_P_to_forward(*n, pg.buf, c0, c1, true);
+        if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(out + off_P + 4 * (size_t)c0 * colsz, pg.buf, 4 * (size_t)(c1 - c0) * colsz,
+                          hipMemcpyDeviceToHost);
+    }
     if (e != hipSuccess) return fail(DPSNN_E_DEVICE, hipGetErrorString(e));
     return DPSNN_OK;
 }
@@ -1176,22 +1365,33 @@ int dpsnn_load(const void* buf, uint64_t size, const dpsnn_device* dev, dpsnn_ne
         }
     }
     const std::vector<CkptPart> parts = ckpt_parts(*n, hd.stim_n);
-    float* Pf = nullptr;
-    if (hipMalloc((void**)&Pf, sizeof(float) * std::max<uint64_t>(n->S, 1)) != hipSuccess) {
-        release(n);
-        return fail(DPSNN_E_NOMEM, "temporary P buffer");
-    }
     hipError_t e = hipSuccess;
     size_t off = pad16(sizeof(CkptHeader));
+    size_t off_P = 0;
     for (size_t k = 0; k + 3 < parts.size(); ++k) {
         const CkptPart& q = parts[k];
-        if (e == hipSuccess && q.bytes)
-            e = hipMemcpy(q.dev ? q.dev : (void*)Pf, in + off, q.bytes, hipMemcpyHostToDevice);
+        if (k == kCkptP) off_P = off;
+        else if (e == hipSuccess && q.bytes) e = hipMemcpy(q.dev, in + off, q.bytes, hipMemcpyHostToDevice);
         off += pad16(q.bytes);
     }
-    if (e == hipSuccess) e = launch_gather_P(*n, Pf);
-    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
-    (void)hipFree(Pf);
+    {
+        // P from the forward layout, a group of source columns at a time
+        PGroups pg;
+        if (e == hipSuccess && !alloc_pgroups(n, pg)) {
+            release(n);
+            return fail(DPSNN_E_NOMEM, "checkpoint P buffer (one column)");
+        }
+        const uint64_t colsz = (uint64_t)n->d.Ncol * n->d.M;
+        for (uint32_t c0 = 0; c0 < n->d.C && e == hipSuccess; c0 += pg.group) {
+            const uint32_t c1 = std::min<uint32_t>(n->d.C, c0 + pg.group);
+            e = hipStreamSynchronize(n->stream);  // the previous group has been consumed
+            if (e == hipSuccess)
+                e = hipMemcpy(pg.buf, in + off_P + 4 * (size_t)c0 * colsz, 4 * (size_t)(c1 - c0) * colsz,
+                              hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = launch_P_from_forward(*n, pg.buf, c0, c1);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    }
     if (e != hipSuccess) {
         release(n);
         return fail(DPSNN_E_DEVICE, std::string("checkpoint upload failed: ") + hipGetErrorString(e));

@@ -80,6 +80,11 @@ struct NetDesc {
     unsigned long long* ev_key;
     float* ev_w;
     uint32_t* cursor;
+    // state probes (null / 0 when none): v and u of probe_n chosen neurons
+    // after each step, in a ring of R rows laid out [slot][v | u][probe]
+    const uint32_t* probe_id;
+    float* probe_buf;
+    uint32_t probe_n;
 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, multipliers

@@ -81,6 +81,9 @@ struct LaunchSet {
     hipStream_t cap_stream = nullptr;
     uint32_t graph_steps = 0;
     Tuning graph_tune;
+    uint32_t graph_probes = 0;
+    // most state probes of one member (0: no probe kernel in the step)
+    uint32_t max_probes = 0;
     // host copies of the uploaded tables (t0 mirrors the device descriptors)
     std::vector<NetDesc> host_descs;
     std::vector<uint2> host_col, host_neu;
@@ -149,6 +152,12 @@ struct Net {
     uint32_t* ev_start = nullptr; // [N+1]
     unsigned long long* ev_key = nullptr;  // [S]
     float* ev_w = nullptr;        // [S]
+    // state probes: v and u of chosen neurons after every step (the paper's
+    // optional trace of individual neurons' state variables)
+    uint32_t* probe_id = nullptr; // [probe_n]
+    float* probe_buf = nullptr;   // [R][2][probe_n]
+    uint32_t probe_n = 0;
+    uint32_t probe_from = 0;      // first step count recorded
 
     // stimulus, sorted by step (stable)
     uint32_t* stim_t = nullptr;
@@ -193,13 +202,16 @@ hipError_t launch_step_set(LaunchSet& L, const Tuning& tune, Timers& tm, hipStre
 // n_steps steps of the set, runs of tune.graph steps as captured graphs.
 hipError_t launch_steps(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
                         Net* const* members, uint32_t n_steps);
-hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, float* Pf, uint32_t* tgt_out,
+hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, uint64_t g_lo, uint64_t g_hi,
+                            const float* Pg, uint64_t pg_base, uint32_t* tgt_out,
                             uint8_t* dly_out, float* w_out, float* P_out, float* D_out);
 // P between the reverse order (whose order inside a row depends on the build's
-// atomics) and the forward layout (fixed by the configuration): Pf has S
-// entries, zero at inhibitory positions.
-hipError_t launch_scatter_P(Net& n, float* Pf);
-hipError_t launch_gather_P(Net& n, const float* Pf);
+// atomics) and the forward layout (fixed by the configuration), for the
+// source columns [c0, c1): Pg holds their forward blocks back to back
+// ((c1 - c0) * Ncol * M floats).  To the forward layout, inhibitory positions
+// are left as they are unless zero_first clears the range first.
+hipError_t launch_P_to_forward(Net& n, float* Pg, uint32_t c0, uint32_t c1, bool zero_first);
+hipError_t launch_P_from_forward(Net& n, float* Pg, uint32_t c0, uint32_t c1);
 hipError_t scan_u32(Net& n, hipStream_t stream, const uint32_t* in, uint32_t* out, uint32_t count);
 hipError_t scan_u32_u64(Net& n, hipStream_t stream, const uint32_t* in, uint64_t* out, uint32_t count);
 

@@ -3,6 +3,8 @@
 // placed it, which locates every synapse's forward position.
 #include "net.h"
 
+#include <algorithm>
+
 namespace dpsnn {
 
 namespace {
@@ -16,14 +18,19 @@ __device__ __forceinline__ unsigned long long same_delay_r(unsigned long long ac
     return m;
 }
 
+// Rows [i0, i1); only canonical synapses g in [g_lo, g_hi) are written, at
+// g - g_lo.  Pg holds P of whole source columns in the forward layout, its
+// first entry being forward position pg_base (the excitatory positions of
+// the rows' columns are all present; inhibitory synapses have P = 0).
 template <typename TgtT>
 __global__ __launch_bounds__(256) void k_read_rows(Dims d, const uint32_t* __restrict__ colmap,
                                                    const uint64_t* __restrict__ seg_off,
                                                    const TgtT* __restrict__ tgt,
                                                    const float* __restrict__ w,
                                                    const float* __restrict__ Dacc,
-                                                   const float* __restrict__ Pf, uint32_t i0,
-                                                   uint32_t i1, uint32_t* __restrict__ o_tgt,
+                                                   const float* __restrict__ Pg, uint64_t pg_base,
+                                                   uint32_t i0, uint32_t i1, uint64_t g_lo,
+                                                   uint64_t g_hi, uint32_t* __restrict__ o_tgt,
                                                    uint8_t* __restrict__ o_dly,
                                                    float* __restrict__ o_w, float* __restrict__ o_P,
                                                    float* __restrict__ o_D) {
@@ -45,89 +52,101 @@ __global__ __launch_bounds__(256) void k_read_rows(Dims d, const uint32_t* __res
         const unsigned long long mine = same_delay_r(act, bb, s.delay);
         const uint32_t rank = (uint32_t)__popcll(mine & lanemask_lt());
         const uint32_t before = __shfl(placed, (int)(s.delay - 1u), 64);
-        if (valid) {
+        const uint64_t g = (uint64_t)row * d.M + j;
+        if (valid && g >= g_lo && g < g_hi) {
             const uint64_t pos =
                 seg_off[(size_t)c * d.segs + (s.delay - 1u) * d.Ncol + l] + before + rank;
-            const size_t o = (size_t)(row - i0) * d.M + j;
+            const size_t o = (size_t)(g - g_lo);
             const uint32_t wi = (uint32_t)tgt[pos];
             const uint32_t sl = wi / d.Ncol;
             if (o_tgt) o_tgt[o] = colmap[c * kSlots + sl] * d.Ncol + (wi - sl * d.Ncol);
             if (o_dly) o_dly[o] = (uint8_t)s.delay;
             if (o_w) o_w[o] = w[pos];
             if (o_D) o_D[o] = Dacc[pos];
-            if (o_P) o_P[o] = Pf[pos];
+            if (o_P) o_P[o] = s.exc ? Pg[pos - pg_base] : 0.0f;
         }
         placed += (uint32_t)__popcll(same_delay_r(act, bb, lane + 1));
     }
 }
 
-// P from reverse to forward order.  Workgroups (target column ct, slice y):
-// an entry's source column is the column that reaches ct through the entry's
-// slot, and its forward position is that column's block start plus rev_fwd.
-__global__ __launch_bounds__(256) void k_scatter_P(Dims d, const uint32_t* __restrict__ srcmap,
-                                                   const uint64_t* __restrict__ rowptr,
-                                                   const uint32_t* __restrict__ rev_srcd,
-                                                   const uint32_t* __restrict__ rev_fwd,
-                                                   const float* __restrict__ P,
-                                                   float* __restrict__ Pf) {
+// P between the reverse order and the forward layout, for the source columns
+// [c0, c1) only.  Pg holds those columns' forward blocks back to back (entry
+// (c - c0) * Ncol * M + offset in the block).  Workgroups (target column ct,
+// slice y): a reverse entry's source column is the column that reaches ct
+// through the entry's slot, its forward offset in that column's block is
+// rev_fwd; target columns that no column of the range reaches return at once.
+template <bool TO_FWD>
+__global__ __launch_bounds__(256) void k_move_P(Dims d, const uint32_t* __restrict__ srcmap,
+                                                const uint64_t* __restrict__ rowptr,
+                                                const uint32_t* __restrict__ rev_srcd,
+                                                const uint32_t* __restrict__ rev_fwd,
+                                                float* __restrict__ P, float* __restrict__ Pg,
+                                                uint32_t c0, uint32_t c1) {
+    __shared__ uint32_t smap[kSlots];
     const uint32_t ct = blockIdx.x;
+    if (threadIdx.x < kSlots) smap[threadIdx.x] = srcmap[ct * kSlots + threadIdx.x];
+    __syncthreads();
+    const uint32_t span = c1 - c0;
+    bool reached = false;
+#pragma unroll
+    for (int q = 0; q < kSlots; ++q) reached |= smap[q] - c0 < span;
+    if (!reached) return;  // workgroup-uniform
+    const uint64_t colsz = (uint64_t)d.Ncol * d.M;
     const uint64_t x0 = rowptr[(size_t)ct * d.Ncol], x1 = rowptr[(size_t)(ct + 1) * d.Ncol];
     const uint64_t stride = (uint64_t)gridDim.y * blockDim.x;
     for (uint64_t x = x0 + (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; x < x1; x += stride) {
-        const uint32_t src = srcmap[ct * kSlots + (rev_srcd[x] >> 22)];
-        Pf[(uint64_t)src * d.Ncol * d.M + rev_fwd[x]] = P[x];
+        const uint32_t rel = smap[rev_srcd[x] >> 22] - c0;
+        if (rel >= span) continue;
+        float* pf = Pg + (uint64_t)rel * colsz + rev_fwd[x];
+        if (TO_FWD) *pf = P[x];
+        else P[x] = *pf;
     }
 }
 
-// The inverse: P[x] = Pf[forward position of x].
-__global__ __launch_bounds__(256) void k_gather_P(Dims d, const uint32_t* __restrict__ srcmap,
-                                                  const uint64_t* __restrict__ rowptr,
-                                                  const uint32_t* __restrict__ rev_srcd,
-                                                  const uint32_t* __restrict__ rev_fwd,
-                                                  const float* __restrict__ Pf,
-                                                  float* __restrict__ P) {
-    const uint32_t ct = blockIdx.x;
-    const uint64_t x0 = rowptr[(size_t)ct * d.Ncol], x1 = rowptr[(size_t)(ct + 1) * d.Ncol];
-    const uint64_t stride = (uint64_t)gridDim.y * blockDim.x;
-    for (uint64_t x = x0 + (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; x < x1; x += stride) {
-        const uint32_t src = srcmap[ct * kSlots + (rev_srcd[x] >> 22)];
-        P[x] = Pf[(uint64_t)src * d.Ncol * d.M + rev_fwd[x]];
-    }
+__global__ __launch_bounds__(256) void k_fill_zero(float* __restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) p[x] = 0.0f;
 }
 
 }  // namespace
 
-hipError_t launch_gather_P(Net& n, const float* Pf) {
-    if (n.S_exc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_P, dim3(n.d.C, 16), dim3(256), 0, n.stream, n.d, n.srcmap,
-                       n.rowptr, n.rev_srcd, n.rev_fwd, Pf, n.Pacc);
+hipError_t launch_P_to_forward(Net& n, float* Pg, uint32_t c0, uint32_t c1, bool zero_first) {
+    if (c1 <= c0) return hipSuccess;
+    if (zero_first) {
+        const uint64_t cnt = (uint64_t)(c1 - c0) * n.d.Ncol * n.d.M;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((cnt + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, n.stream, Pg, cnt);
+    }
+    if (n.S_exc == 0) return hipGetLastError();
+    hipLaunchKernelGGL(k_move_P<true>, dim3(n.d.C, 16), dim3(256), 0, n.stream, n.d, n.srcmap,
+                       n.rowptr, n.rev_srcd, n.rev_fwd, n.Pacc, Pg, c0, c1);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_P(Net& n, float* Pf) {
-    hipError_t e = hipMemsetAsync(Pf, 0, sizeof(float) * n.S, n.stream);
-    if (e != hipSuccess) return e;
-    if (n.S_exc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter_P, dim3(n.d.C, 16), dim3(256), 0, n.stream, n.d, n.srcmap,
-                       n.rowptr, n.rev_srcd, n.rev_fwd, n.Pacc, Pf);
+hipError_t launch_P_from_forward(Net& n, float* Pg, uint32_t c0, uint32_t c1) {
+    if (c1 <= c0 || n.S_exc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_move_P<false>, dim3(n.d.C, 16), dim3(256), 0, n.stream, n.d, n.srcmap,
+                       n.rowptr, n.rev_srcd, n.rev_fwd, n.Pacc, Pg, c0, c1);
     return hipGetLastError();
 }
 
-// Rows [i0, i1) (canonical synapses i0*M .. i1*M) into device outputs laid out
-// (row - i0) * M + j.  Pf: P in forward layout (from launch_scatter_P) or null.
-hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, float* Pf, uint32_t* tgt_out,
+// Canonical synapses [g_lo, g_hi) of rows [i0, i1) into device outputs at
+// g - g_lo.  Pg: P of whole source columns in the forward layout starting at
+// forward position pg_base (from launch_P_to_forward), or null.
+hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, uint64_t g_lo, uint64_t g_hi,
+                            const float* Pg, uint64_t pg_base, uint32_t* tgt_out,
                             uint8_t* dly_out, float* w_out, float* P_out, float* D_out) {
     const uint32_t rows = i1 - i0;
     if (rows == 0) return hipSuccess;
     const uint32_t gb = (rows + 3) / 4;
     if (n.tgt16) {
         hipLaunchKernelGGL(k_read_rows<uint16_t>, dim3(gb), dim3(256), 0, n.stream, n.d, n.colmap,
-                           n.seg_off, (const uint16_t*)n.tgt, n.w, n.Dacc, Pf, i0, i1, tgt_out,
-                           dly_out, w_out, P_out, D_out);
+                           n.seg_off, (const uint16_t*)n.tgt, n.w, n.Dacc, Pg, pg_base, i0, i1,
+                           g_lo, g_hi, tgt_out, dly_out, w_out, P_out, D_out);
     } else {
         hipLaunchKernelGGL(k_read_rows<uint32_t>, dim3(gb), dim3(256), 0, n.stream, n.d, n.colmap,
-                           n.seg_off, (const uint32_t*)n.tgt, n.w, n.Dacc, Pf, i0, i1, tgt_out,
-                           dly_out, w_out, P_out, D_out);
+                           n.seg_off, (const uint32_t*)n.tgt, n.w, n.Dacc, Pg, pg_base, i0, i1,
+                           g_lo, g_hi, tgt_out, dly_out, w_out, P_out, D_out);
     }
     return hipGetLastError();
 }

@@ -47,6 +47,7 @@ struct Job {
     int error = 0;
     std::string message;
     Net* net = nullptr;
+    bool cancel = false;          // dpsnn_server_cancel asked for it (guarded by mu)
     uint32_t launched = 0;
     double t_submit = 0, t_admit = 0, t_built = 0, t_done = 0;
 };
@@ -170,6 +171,12 @@ void dpsnn_server::builder_main() {
             continue;
         }
         j->net = n;
+        if (j->cancel) {  // cancelled while it was being built: never stepped
+            j->t_built = now();
+            finish_locked(j, j->t_built, DPSNN_E_CANCELED, "cancelled");
+            cv_done.notify_all();
+            continue;
+        }
         j->t_built = now();
         ready.push_back(j);
         cv_ready.notify_one();
@@ -245,11 +252,19 @@ void dpsnn_server::stepper_main() {
             if (active.empty() && inflight.empty())
                 cv_ready.wait(lk, [&] { return stop || !ready.empty(); });
             if (stop) break;
+            bool dropped = false;
             while (!ready.empty()) {
-                active.push_back(ready.front());
+                Job* j = ready.front();
                 ready.pop_front();
+                if (j->cancel) {  // built but never stepped
+                    finish_locked(j, now(), DPSNN_E_CANCELED, "cancelled");
+                    dropped = true;
+                    continue;
+                }
+                active.push_back(j);
                 regroup = true;
             }
+            if (dropped) cv_done.notify_all();
         }
         if (active.empty()) {  // nothing to launch: retire what is in flight
             complete(inflight.front(), pool);
@@ -292,6 +307,7 @@ void dpsnn_server::stepper_main() {
             (void)hipEventDestroy(qm.ev);
             qm.ev = nullptr;
         }
+        std::vector<Job*> keep;
         {
             std::lock_guard<std::mutex> lk(mu);
             st.quanta++;
@@ -300,17 +316,22 @@ void dpsnn_server::stepper_main() {
                 st.job_steps += j->net->t - j->launched;
                 j->launched = j->net->t;
             }
-        }
-        std::vector<Job*> keep;
-        for (Job* j : active) {
-            if (err) {
-                j->error = err;
-                j->message = msg;
-                qm.finishing.push_back(j);
-            } else if (j->net->t >= j->steps) {
-                qm.finishing.push_back(j);
-            } else {
-                keep.push_back(j);
+            // a job leaves after this quantum when it failed, finished or was
+            // cancelled; its network is touched by no later quantum
+            for (Job* j : active) {
+                if (err) {
+                    j->error = err;
+                    j->message = msg;
+                    qm.finishing.push_back(j);
+                } else if (j->net->t >= j->steps) {
+                    qm.finishing.push_back(j);
+                } else if (j->cancel) {
+                    j->error = DPSNN_E_CANCELED;
+                    j->message = "cancelled";
+                    qm.finishing.push_back(j);
+                } else {
+                    keep.push_back(j);
+                }
             }
         }
         if (keep.size() != active.size()) regroup = true;
@@ -486,6 +507,27 @@ int dpsnn_server_wait(dpsnn_server* s, uint64_t job, double timeout_s, dpsnn_job
     if (it == s->jobs.end()) return fail(DPSNN_E_INVAL, "the job was released while waiting");
     fill_info(*it->second, info);
     if (!ok || !is_final(it->second->status)) return fail(DPSNN_E_TIMEOUT, "the job has not finished");
+    // collected here: dpsnn_server_wait_any will not return it again
+    auto f = std::find(s->finished.begin(), s->finished.end(), job);
+    if (f != s->finished.end()) s->finished.erase(f);
+    return DPSNN_OK;
+}
+
+int dpsnn_server_cancel(dpsnn_server* s, uint64_t job) {
+    if (!s) return fail(DPSNN_E_INVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(job);
+    if (it == s->jobs.end()) return fail(DPSNN_E_INVAL, "unknown or released job");
+    Job* j = it->second.get();
+    if (is_final(j->status)) return fail(DPSNN_E_INVAL, "the job has already finished");
+    j->cancel = true;
+    if (j->status == DPSNN_JOB_QUEUED) {
+        auto q = std::find(s->queue.begin(), s->queue.end(), j);
+        if (q != s->queue.end()) s->queue.erase(q);
+        s->finish_locked(j, s->now(), DPSNN_E_CANCELED, "cancelled");
+        s->cv_done.notify_all();
+        s->cv_admit.notify_one();  // the next job may now be at the head
+    }
     return DPSNN_OK;
 }
 

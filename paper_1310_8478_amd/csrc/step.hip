@@ -1136,6 +1136,22 @@ __global__ __launch_bounds__(256) void k_wupdate(const NetDesc* __restrict__ nds
     }
 }
 
+// State probes (Sec. 2, "Production of observables": the trace of the
+// membrane potential and other state variables of individual neurons): after
+// the neuron update of step t, v and u of each probed neuron into row
+// (t + 1) % R of the network's probe ring.  Workgroups (chunk x, member y).
+__global__ __launch_bounds__(256) void k_probe(const NetDesc* __restrict__ nds, uint32_t tstep) {
+    const NetDesc& nd = nds[blockIdx.y];
+    const uint32_t n = nd.probe_n;
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t t = nd.t0 + tstep;
+    float* row = nd.probe_buf + (size_t)((t + 1u) % nd.d.R) * 2u * n;
+    const uint32_t k = nd.probe_id[p];
+    row[p] = nd.v[k];
+    row[n + p] = nd.u[k];
+}
+
 // t0 += delta for each of the K descriptors of a launch set
 __global__ __launch_bounds__(64) void k_rebase(NetDesc* __restrict__ nds, uint32_t K, uint32_t delta) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1440,6 +1456,11 @@ hipError_t enqueue_step(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_
         hipLaunchKernelGGL(k_neuron<DPSNN_SUM_ORDERED>, dim3(L.n_neu), dim3(256), 0, stream, L.descs, L.bmap_neu, tstep);
     tm.end(stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (L.max_probes) {
+        hipLaunchKernelGGL(k_probe, dim3((L.max_probes + 255u) / 256u, L.K), dim3(256), 0, stream,
+                           L.descs, tstep);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     for (uint32_t k = 0; wu && k < L.K; ++k) {
         if (!wu[k]) continue;
         const Net& n = *members[k];
@@ -1480,7 +1501,8 @@ hipError_t launch_graph(LaunchSet& L, const Tuning& tune, hipStream_t stream, Ne
     hipError_t e;
     uint32_t tstep;
     if (!set_tstep(L, members, tstep)) return hipErrorInvalidValue;
-    if (L.graph && (L.graph_steps != G || !same_shapes(L.graph_tune, tune))) {
+    if (L.graph && (L.graph_steps != G || !same_shapes(L.graph_tune, tune) ||
+                    L.graph_probes != L.max_probes)) {
         (void)hipGraphExecDestroy(L.graph);
         L.graph = nullptr;
     }
@@ -1512,6 +1534,7 @@ hipError_t launch_graph(LaunchSet& L, const Tuning& tune, hipStream_t stream, Ne
         }
         L.graph_steps = G;
         L.graph_tune = tune;
+        L.graph_probes = L.max_probes;
     }
     if ((e = hipGraphLaunch(L.graph, stream)) != hipSuccess) return e;
     for (uint32_t k = 0; k < L.K; ++k) {
@@ -1564,9 +1587,16 @@ hipError_t launch_steps(LaunchSet& L, const Tuning& tune_in, Timers& tm, hipStre
         bool graphed = G && n_steps - s >= G && !tm.on && L.K && L.sum_mode != DPSNN_SUM_ORDERED;
         for (uint32_t k = 0; graphed && k < L.K; ++k)
             graphed = members[k]->t >= 1 && steps_to_consolidation(L, *members[k], k) >= G;
+        const Tuning eff = effective_tuning(L, tune_in);
+        // a capture costs about as much as several steps of a small network:
+        // capture only when this call replays the graph at least 4 times, or
+        // reuse one captured before with the same run length and shapes
+        if (graphed && n_steps - s < 4u * G)
+            graphed = L.graph && L.graph_steps == G && same_shapes(L.graph_tune, eff) &&
+                      L.graph_probes == L.max_probes;
         hipError_t e;
         if (graphed) {
-            e = launch_graph(L, effective_tuning(L, tune_in), stream, members, G);
+            e = launch_graph(L, eff, stream, members, G);
             s += G;
         } else {
             e = launch_step_set(L, tune_in, tm, stream, members);

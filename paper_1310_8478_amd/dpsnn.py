@@ -15,7 +15,7 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdpsnn.so")
 
-E_INVAL, E_NOMEM, E_DEVICE, E_RANGE, E_BUFSZ, E_TIMEOUT = -1, -2, -3, -4, -5, -6
+E_INVAL, E_NOMEM, E_DEVICE, E_RANGE, E_BUFSZ, E_TIMEOUT, E_CANCELED = -1, -2, -3, -4, -5, -6, -7
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 SUM_ORDERED, SUM_ATOMIC, SUM_FIXED = 0, 1, 2
 
@@ -83,12 +83,13 @@ EXPORTS = [
     "dpsnn_default_config", "dpsnn_footprint_bytes", "dpsnn_build_network", "dpsnn_step",
     "dpsnn_sync", "dpsnn_time", "dpsnn_read_spikes", "dpsnn_read_weights",
     "dpsnn_read_connectivity", "dpsnn_read_state", "dpsnn_get_stats", "dpsnn_set_stimulus",
+    "dpsnn_set_probes", "dpsnn_read_probes",
     "dpsnn_set_timing", "dpsnn_set_tuning", "dpsnn_autotune", "dpsnn_destroy",
     "dpsnn_get_config", "dpsnn_checkpoint_bytes", "dpsnn_save", "dpsnn_load",
     "dpsnn_batch_create", "dpsnn_batch_step", "dpsnn_batch_get_stats", "dpsnn_batch_set_timing",
     "dpsnn_batch_set_tuning", "dpsnn_batch_autotune", "dpsnn_batch_destroy",
     "dpsnn_server_create", "dpsnn_server_submit", "dpsnn_server_query", "dpsnn_server_wait",
-    "dpsnn_server_wait_any", "dpsnn_server_release", "dpsnn_server_get_stats", "dpsnn_server_clock",
+    "dpsnn_server_wait_any", "dpsnn_server_cancel", "dpsnn_server_release", "dpsnn_server_get_stats", "dpsnn_server_clock",
     "dpsnn_server_destroy", "dpsnn_last_error",
 ]
 _VOID = ("dpsnn_destroy", "dpsnn_batch_destroy", "dpsnn_server_destroy", "dpsnn_last_error")
@@ -120,6 +121,8 @@ def lib():
         L.dpsnn_read_state.argtypes = [vp, P(C.c_float), P(C.c_float)]
         L.dpsnn_get_stats.argtypes = [vp, P(dpsnn_stats)]
         L.dpsnn_set_stimulus.argtypes = [vp, P(C.c_uint32), P(C.c_uint32), P(C.c_float), C.c_size_t]
+        L.dpsnn_set_probes.argtypes = [vp, P(C.c_uint32), C.c_uint32]
+        L.dpsnn_read_probes.argtypes = [vp, C.c_uint32, C.c_uint32, P(C.c_float), P(C.c_float)]
         L.dpsnn_set_timing.argtypes = [vp, C.c_int]
         L.dpsnn_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32]
         L.dpsnn_autotune.argtypes = [vp, C.c_uint32]
@@ -143,6 +146,7 @@ def lib():
         L.dpsnn_server_query.argtypes = [vp, C.c_uint64, P(dpsnn_job_info)]
         L.dpsnn_server_wait.argtypes = [vp, C.c_uint64, C.c_double, P(dpsnn_job_info)]
         L.dpsnn_server_wait_any.argtypes = [vp, C.c_double, P(dpsnn_job_info)]
+        L.dpsnn_server_cancel.argtypes = [vp, C.c_uint64]
         L.dpsnn_server_release.argtypes = [vp, C.c_uint64]
         L.dpsnn_server_get_stats.argtypes = [vp, P(dpsnn_server_stats)]
         L.dpsnn_server_clock.argtypes = [vp, P(C.c_double)]
@@ -208,15 +212,19 @@ class _TorchAllocator:
 class Network:
     """One simulated network on one GPU (dpsnn_build_network .. dpsnn_destroy)."""
 
-    def __init__(self, cfg: dict, device: int = 0, stream=None, torch_alloc: bool = True):
+    def __init__(self, cfg: dict, device: int = 0, stream=None, torch_alloc: bool = True,
+                 allocator=None):
         self.cfg = dict(cfg)
         self._c = to_config(cfg)
-        dev = self._device(device, stream, torch_alloc)
+        dev = self._device(device, stream, torch_alloc, allocator)
         h = C.c_void_p()
         _check(lib().dpsnn_build_network(C.byref(self._c), C.byref(dev), C.byref(h)))
         self._adopt(h)
 
-    def _device(self, device, stream, torch_alloc):
+    def _device(self, device, stream, torch_alloc, allocator=None):
+        """allocator: an object with ctypes `alloc` / `free` callbacks
+        (ALLOC_FN, FREE_FN) serving every device allocation of the network;
+        by default PyTorch's caching allocator (torch_alloc) or hipMalloc."""
         self._allocator = None
         dev = dpsnn_device()
         dev.device = device
@@ -228,8 +236,11 @@ class Network:
             except Exception:
                 stream = 0
         dev.stream = stream or None
-        if torch_alloc:
+        if allocator is not None:
+            self._allocator = allocator
+        elif torch_alloc:
             self._allocator = _TorchAllocator(device)
+        if self._allocator is not None:
             dev.alloc = self._allocator.alloc
             dev.free = self._allocator.free
         dev.ctx = None
@@ -254,14 +265,14 @@ class Network:
         return buf
 
     @classmethod
-    def load(cls, src, device: int = 0, stream=None, torch_alloc: bool = True):
+    def load(cls, src, device: int = 0, stream=None, torch_alloc: bool = True, allocator=None):
         """A network restored from a checkpoint (a path or the bytes of one)."""
         if isinstance(src, (str, os.PathLike)):
             buf = np.fromfile(src, dtype=np.uint8)
         else:
             buf = np.ascontiguousarray(np.frombuffer(src, dtype=np.uint8))
         self = cls.__new__(cls)
-        dev = self._device(device, stream, torch_alloc)
+        dev = self._device(device, stream, torch_alloc, allocator)
         h = C.c_void_p()
         _check(lib().dpsnn_load(buf.ctypes.data, buf.size, C.byref(dev), C.byref(h)))
         c = dpsnn_config()
@@ -372,6 +383,21 @@ class Network:
         mv = np.ascontiguousarray(mv, dtype=np.float32)
         _check(lib().dpsnn_set_stimulus(self.h, _ptr(t, C.c_uint32), _ptr(ids, C.c_uint32),
                                         _ptr(mv, C.c_float), len(t)))
+
+    def set_probes(self, ids):
+        """Record v and u of these neurons after every later step."""
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        _check(lib().dpsnn_set_probes(self.h, _ptr(ids, C.c_uint32), len(ids)))
+        self._nprobe = len(ids)
+
+    def read_probes(self, t_begin: int, t_end: int):
+        """Probed (v, u) after steps t_begin .. t_end - 1, arrays of shape
+        (t_end - t_begin, number of probes)."""
+        n = getattr(self, "_nprobe", 0)
+        v = np.zeros((t_end - t_begin, n), dtype=np.float32)
+        u = np.zeros((t_end - t_begin, n), dtype=np.float32)
+        _check(lib().dpsnn_read_probes(self.h, t_begin, t_end, _ptr(v, C.c_float), _ptr(u, C.c_float)))
+        return v, u
 
     def set_timing(self, enable: bool = True):
         _check(lib().dpsnn_set_timing(self.h, int(bool(enable))))
@@ -514,6 +540,11 @@ class Server:
         if info["status"] != JOB_DONE or not info["net"]:
             raise DpsnnError(E_INVAL, f"job {job} is not done")
         return Network._view(info["net"], self._cfgs[job])
+
+    def cancel(self, job: int):
+        """Ask the server to stop a queued or running job (it becomes FAILED
+        with E_CANCELED at the next quantum boundary)."""
+        _check(lib().dpsnn_server_cancel(self.h, job))
 
     def release(self, job: int):
         _check(lib().dpsnn_server_release(self.h, job))

@@ -99,6 +99,7 @@ def test_server_argument_checks(dp):
     assert L.dpsnn_server_wait_any(None, 0.0, C.byref(info)) == dp.E_INVAL
     assert L.dpsnn_server_wait(None, 1, 0.0, C.byref(info)) == dp.E_INVAL
     assert L.dpsnn_server_release(None, 1) == dp.E_INVAL
+    assert L.dpsnn_server_cancel(None, 1) == dp.E_INVAL
     assert L.dpsnn_server_query(None, 1, C.byref(info)) == dp.E_INVAL
     L.dpsnn_server_destroy(None)
     assert C.sizeof(dp.dpsnn_job_info) == 8 + 4 + 4 + 4 + 4 + 8 + 4 * 8 + 8 + 160
@@ -179,3 +180,24 @@ def test_checkpoint_contents_checked_on_host(dp):
     big, _, _ = _checkpoint_image(dp, cfg, R, extra=16)
     rc, msg = _load(dp, big)
     assert rc == dp.E_INVAL and "size" in msg, msg
+
+
+def test_device_allocations_only_in_the_allocator_helpers():
+    # every device allocation of the library goes through the network's (or
+    # server's) allocator: the only direct runtime allocations are the
+    # fallbacks of the helpers used when no callbacks are given
+    import re
+    csrc = os.path.join(ROOT, "paper_1310_8478_amd", "csrc")
+    found = {}
+    for fn in sorted(os.listdir(csrc)):
+        txt = open(os.path.join(csrc, fn)).read()
+        for m in re.finditer(r"\bhip(Malloc|MallocAsync|MallocManaged|ExtMallocWithFlags|HostMalloc)\s*\(", txt):
+            # the function the call sits in: the last line that opens a
+            # top-level definition before it
+            head = txt[:m.start()]
+            fdef = re.findall(r"^[A-Za-z].*?\b([A-Za-z_][A-Za-z_0-9]*)\s*\([^;]*$", head, re.M)
+            found.setdefault(fn, []).append((m.group(0).split("(")[0], fdef[-1] if fdef else None))
+    assert found.get("api.cpp") == [("hipMalloc", "dalloc"), ("hipMalloc", "dev_alloc"),
+                                    ("hipHostMalloc", "make_launch_set")], found
+    assert found.get("serve.cpp") == [("hipMallocAsync", "ordered_alloc")], found
+    assert set(found) == {"api.cpp", "serve.cpp"}, found

@@ -201,3 +201,38 @@ def test_graph_atomic_mode_accounting(dp):
         assert st["events"] == int(cum[ii[ok].astype(np.int64), lim[ok]].sum())
     finally:
         net.close()
+
+
+def test_graph_autotuned_batch_members_equal_oracle(dp, orc):
+    # the batched path as a caller runs it: autotuned launch shapes, then
+    # runs of 8 steps replayed from captured graphs (with each member's own
+    # consolidations launched directly), every member against the oracle
+    T = 230
+    _say("autotuned batch of 4 uneven networks replayed from graphs vs the oracle")
+    nets = [dp.Network(c) for c in MIX]
+    b = dp.Batch(nets)
+    try:
+        b.autotune(3)             # 2 rounds x 6 shapes x 3 steps = 36 steps
+        b.step(T - 36)
+        st = b.stats()
+        assert st["steps"] == 4 * T
+        assert st["graph_steps"] >= 4 * 120, st["graph_steps"]
+        b.close()
+        for j, (cfg, n) in enumerate(zip(MIX, nets)):
+            got = _snap(n)
+            o = orc.Net(cfg, T)
+            o.run(T)
+            ot, oi = o.raster()
+            s = o.synapses()
+            ov, ou = o.state()
+            o.close()
+            assert len(ot) > 100
+            np.testing.assert_array_equal(got["tt"], ot, err_msg=f"member {j}")
+            np.testing.assert_array_equal(got["ii"], oi, err_msg=f"member {j}")
+            for key, r in (("w", s["w"]), ("P", s["P"]), ("D", s["D"]), ("v", ov), ("u", ou)):
+                np.testing.assert_array_equal(got[key].view(np.uint32), r.view(np.uint32),
+                                              err_msg=f"member {j} {key}")
+    finally:
+        b.close()
+        for n in nets:
+            n.close()

@@ -276,6 +276,32 @@ def test_atomic_mode_statistics(dp, orc):
     assert l1 <= 0.02, l1
 
 
+def test_atomic_mode_statistics_mid_cut_down(dp, orc):
+    # the mid workload's column shape (1250 neurons, M = 200) on a 6x6 grid,
+    # 1000 steps through the consolidation: the unordered fp32 mode against
+    # the ordered oracle, mean rate within 1 % and the excitatory weights'
+    # histogram (100 bins over [0, 10]) within L1 0.02
+    T = 1000
+    cfg_o = W.mid(grid_x=6, grid_y=6, sum_mode=W.SUM_ORDERED)
+    cfg_a = W.mid(grid_x=6, grid_y=6, sum_mode=W.SUM_ATOMIC)
+    _say("atomic mode statistics, 6x6 cut-down of mid, 1000 steps")
+    g = gpu_run(dp, cfg_a, T, conn=False)
+    o = oracle_run(orc, cfg_o, T)
+    N = 36 * 1250
+    rate_g = len(g["tt"]) / (N * T / 1000.0)
+    rate_o = len(o["tt"]) / (N * T / 1000.0)
+    _say(f"  rate gpu {rate_g:.3f} Hz, oracle {rate_o:.3f} Hz")
+    assert rate_o > 5.0
+    assert abs(rate_g / rate_o - 1.0) <= 0.01, (rate_g, rate_o)
+    exc = (np.repeat(np.arange(N), 200) % 1250) < 1000
+    hg, _ = np.histogram(g["w"][exc], bins=100, range=(0.0, 10.0))
+    ho, _ = np.histogram(o["w"][exc], bins=100, range=(0.0, 10.0))
+    l1 = np.abs(hg / hg.sum() - ho / ho.sum()).sum()
+    _say(f"  weight histogram L1 {l1:.5f}")
+    assert l1 <= 0.02, l1
+    assert g["stats"]["consolidations"] == 1
+
+
 def test_counter_invariants(dp):
     cfg = W.tiny()
     T = 400
@@ -339,10 +365,12 @@ def test_tuning_and_step_arguments(dp):
 
 
 def test_mid_full_size_window_bitexact(dp, orc):
-    # full mid workload (720 k neurons, 144 M synapses), first 60 steps
+    # full mid workload (720 k neurons, 144 M synapses), first 200 steps
+    # (past the start-up transient), in the launch shapes a caller gets;
+    # raster, v and u of every neuron, connectivity, P and D of sampled rows
     cfg = W.mid()
-    T = 60
-    _say("mid full size 60 steps")
+    T = 200
+    _say("mid full size 200 steps (the oracle takes about 90 s)")
     net = dp.Network(cfg)
     net.step(T)
     net.sync()
@@ -361,13 +389,16 @@ def test_mid_full_size_window_bitexact(dp, orc):
     np.testing.assert_array_equal(ii, oi)
     np.testing.assert_array_equal(bits(v), bits(ov))
     np.testing.assert_array_equal(bits(u), bits(ou))
+    nz = 0
     for r, (tg, dl), ws in zip(rows, conn, wts):
         s = n.synapses(int(r) * 200, 200)
         np.testing.assert_array_equal(tg, s["tgt"])
         np.testing.assert_array_equal(dl, s["dly"])
         np.testing.assert_array_equal(bits(ws["D"]), bits(s["D"]))
         np.testing.assert_array_equal(bits(ws["P"]), bits(s["P"]))
+        nz += int((s["P"] != 0).sum() + (s["D"] != 0).sum())
     n.close()
+    assert len(ot) > 100_000 and nz > 100, (len(ot), nz)
 
 
 @pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])

@@ -270,3 +270,56 @@ def test_mixed_summation_modes(dp):
         lim = np.minimum(steps - g["tt"].astype(np.int64), cfg["max_delay"])
         ok = lim >= 1
         assert g["stats"]["events"] == int(cum[g["ii"][ok].astype(np.int64), lim[ok]].sum())
+
+
+def test_cancel_running_and_queued_jobs(dp):
+    # a long job is cancelled while it runs, another while it waits for
+    # memory: both become FAILED (E_CANCELED), their memory returns to the
+    # budget on release, and the jobs that ran beside them equal their solo
+    # runs bit for bit
+    _say("serve: cancel a running and a queued job")
+    long_cfg = W.make_config(grid_x=4, grid_y=4, synapses_per_neuron=200, seed=4101,
+                             raster_steps=1024)
+    keep = [JOBS[0], JOBS[2], JOBS[5]]
+    fp_long = dp.footprint_bytes(long_cfg)
+    fp_keep = sum(dp.footprint_bytes(dict(c, raster_steps=max(s + 1, c["max_delay"] + 1)))
+                  for c, s in keep)
+    # the budget holds the long job and the kept jobs, not a second long job
+    srv = dp.Server(max_quantum=4, budget_bytes=fp_long + fp_keep + (64 << 20))
+    try:
+        j_long = srv.submit(long_cfg, 200000)
+        ids = [srv.submit(c, s) for c, s in keep]
+        j_queued = srv.submit(long_cfg, 100)   # waits: no room beside j_long
+        t0 = time.time()
+        while srv.query(j_long)["steps_launched"] < 50:
+            assert time.time() - t0 < 60, "the long job did not start"
+            time.sleep(0.01)
+        assert srv.query(j_queued)["status"] == dp.JOB_QUEUED
+        srv.cancel(j_queued)
+        info = srv.query(j_queued)
+        assert info["status"] == dp.JOB_FAILED and info["error"] == dp.E_CANCELED
+        srv.cancel(j_long)
+        info = srv.wait(j_long, timeout=60.0)
+        assert info["status"] == dp.JOB_FAILED and info["error"] == dp.E_CANCELED
+        assert info["steps_launched"] < 200000
+        with pytest.raises(dp.DpsnnError) as e:
+            srv.cancel(j_long)            # already finished
+        assert e.value.code == dp.E_INVAL
+        before = srv.stats()["reserved_bytes"]
+        srv.release(j_long)
+        srv.release(j_queued)
+        assert before - srv.stats()["reserved_bytes"] == info["footprint"]
+        got = {}
+        for j, (c, s) in zip(ids, keep):
+            i = srv.wait(j, timeout=120.0)
+            assert i["status"] == dp.JOB_DONE, i
+            got[j] = snapshot(srv.job_network(j), s)
+        # wait() collected them: wait_any returns only the uncollected ones
+        assert srv.wait_any(timeout=0.0) is None
+        for j in ids:
+            srv.release(j)
+        assert srv.stats()["reserved_bytes"] == 0
+    finally:
+        srv.close()
+    for j, (c, s) in zip(ids, keep):
+        assert_same(got[j], solo(dp, c, s), f"job {j} beside the cancelled ones")
