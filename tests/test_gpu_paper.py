@@ -42,8 +42,8 @@ def bits(a):
 @pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
 @pytest.mark.parametrize("k", [0, 1])
 def test_table1_shapes_bitexact(dp, orc, k, mode):
-    cfg = W.paper_table1(k, sum_mode=mode)
     T = 1100
+    cfg = W.paper_table1(k, sum_mode=mode, raster_steps=T + 1)
     _say(f"Table 1 grid {k} ({cfg['grid_x']}x{cfg['grid_y']} x 1000, M = 200), mode {mode}, {T} steps")
     net = dp.Network(cfg)
     try:
