@@ -39,7 +39,7 @@ BYTES_NEURON = 44                   # v, u, current, spike history, latest stamp
 BYTES_CONSOLIDATION = 24            # per excitatory synapse: w, P, D
 
 KERNELS = ("ltp", "deliver", "neuron", "wupdate")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernels_large_hbm_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ltp_deliver_large_hbm_traffic.json")
 
 
 def measured_traffic(workload, steps, first, mode, kernel):

@@ -212,3 +212,26 @@ def stdp_posthoc(cfg, N, times, ids, tgt, dly, T):
             P = np.where(exc, (F(cfg["sd_decay"]) * sd).astype(np.float32), P)
             D = np.where(exc, F(0), D).astype(np.float32)
     return w, P, D
+
+
+# ---------------------------------------------------------------------------
+# Statistical parity of an unordered summation mode.  Once weights are not
+# integers, runs that sum the same currents in different (all valid) orders
+# diverge chaotically, and single bursts decide a run's mean rate (heavy
+# tails): the comparison is over an ensemble of seeds, by the median of the
+# per-seed rate deviations and by the pooled weight histogram.
+# ---------------------------------------------------------------------------
+def ensemble_stats(runs_a, runs_b, exc_mask, bins=100, wmax=10.0):
+    """runs_*: lists of (n_spikes, raster pair (tt, ii), w) per seed, same
+    seeds in the same order.  Returns the median |rate_a / rate_b - 1|, the
+    L1 distance of the pooled excitatory-weight histograms (each normalised),
+    and the number of seeds whose rasters differ."""
+    dev, ha, hb, differ = [], 0, 0, 0
+    for (na, ra, wa), (nb, rb, wb) in zip(runs_a, runs_b):
+        dev.append(abs(na / nb - 1.0))
+        same = len(ra[0]) == len(rb[0]) and (ra[0] == rb[0]).all() and (ra[1] == rb[1]).all()
+        differ += 0 if same else 1
+        ha = ha + np.histogram(wa[exc_mask], bins=bins, range=(0.0, wmax))[0]
+        hb = hb + np.histogram(wb[exc_mask], bins=bins, range=(0.0, wmax))[0]
+    l1 = float(np.abs(ha / ha.sum() - hb / hb.sum()).sum())
+    return float(np.median(dev)), l1, differ

@@ -1,9 +1,12 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
 Bar: bit-exact raster, weights, P, D, v, u and connectivity in the two
-reproducible summation modes (fixed-point and ordered fp32); statistical
-parity (mean rate within 1 %, weight-histogram L1 <= 0.02) in the unordered
-fp32-atomic mode.
+reproducible summation modes (fixed-point and ordered fp32).  The unordered
+fp32-atomic mode is bit-exact while the weights are integers (the workloads'
+1000-step runs); past a consolidation it is held to a statistical bar over
+an ensemble of seeds (median rate deviation within 1 %, pooled
+weight-histogram L1 <= 0.02), the bar the two reproducible orders meet
+against each other.
 """
 import sys
 
@@ -259,47 +262,56 @@ def test_launch_shape_invariance(dp, orc, mode):
         assert_bitexact(g, ref, conn=False)
 
 
-def test_atomic_mode_statistics(dp, orc):
-    T = 1000
-    cfg_o = W.tiny(sum_mode=W.SUM_ORDERED)
-    cfg_a = W.tiny(sum_mode=W.SUM_ATOMIC)
-    _say("atomic mode statistics")
-    g = gpu_run(dp, cfg_a, T, conn=False)
-    o = oracle_run(orc, cfg_o, T)
-    rate_g = len(g["tt"]) / (5000 * T / 1000.0)
-    rate_o = len(o["tt"]) / (5000 * T / 1000.0)
-    assert abs(rate_g / rate_o - 1.0) <= 0.01, (rate_g, rate_o)
-    exc = (np.repeat(np.arange(5000), 100) % 1250) < 1000
-    hg, _ = np.histogram(g["w"][exc], bins=100, range=(0.0, 10.0))
-    ho, _ = np.histogram(o["w"][exc], bins=100, range=(0.0, 10.0))
-    l1 = np.abs(hg / hg.sum() - ho / ho.sum()).sum()
-    assert l1 <= 0.02, l1
+def _exact_same(g, o):
+    np.testing.assert_array_equal(g["tt"], o["tt"])
+    np.testing.assert_array_equal(g["ii"], o["ii"])
+    for k in ("w", "P", "D", "v", "u"):
+        np.testing.assert_array_equal(bits(g[k]), bits(o[k]), err_msg=k)
 
 
-def test_atomic_mode_statistics_mid_cut_down(dp, orc):
-    # the mid workload's column shape (1250 neurons, M = 200) on a 6x6 grid,
-    # 1000 steps through the consolidation: the unordered fp32 mode against
-    # the ordered oracle, mean rate within 1 % and the excitatory weights'
-    # histogram (100 bins over [0, 10]) within L1 0.02
+@pytest.mark.parametrize("shape", ["tiny", "mid_6x6"])
+def test_atomic_mode_exact_at_the_workload_period(dp, orc, shape):
+    # the workloads consolidate every 1000 steps, so over their 1000-step
+    # runs every weight is 6 or -5 and the thalamic input 20 mV: every
+    # current is a sum of small integers, exact in fp32 in any order, and
+    # the unordered mode reproduces the oracle bit for bit (rate ratio 1,
+    # weight-histogram L1 0), the consolidation at the last step included
     T = 1000
-    cfg_o = W.mid(grid_x=6, grid_y=6, sum_mode=W.SUM_ORDERED)
-    cfg_a = W.mid(grid_x=6, grid_y=6, sum_mode=W.SUM_ATOMIC)
-    _say("atomic mode statistics, 6x6 cut-down of mid, 1000 steps")
-    g = gpu_run(dp, cfg_a, T, conn=False)
-    o = oracle_run(orc, cfg_o, T)
-    N = 36 * 1250
-    rate_g = len(g["tt"]) / (N * T / 1000.0)
-    rate_o = len(o["tt"]) / (N * T / 1000.0)
-    _say(f"  rate gpu {rate_g:.3f} Hz, oracle {rate_o:.3f} Hz")
-    assert rate_o > 5.0
-    assert abs(rate_g / rate_o - 1.0) <= 0.01, (rate_g, rate_o)
-    exc = (np.repeat(np.arange(N), 200) % 1250) < 1000
-    hg, _ = np.histogram(g["w"][exc], bins=100, range=(0.0, 10.0))
-    ho, _ = np.histogram(o["w"][exc], bins=100, range=(0.0, 10.0))
-    l1 = np.abs(hg / hg.sum() - ho / ho.sum()).sum()
-    _say(f"  weight histogram L1 {l1:.5f}")
-    assert l1 <= 0.02, l1
+    mk = W.tiny if shape == "tiny" else (lambda **k: W.mid(grid_x=6, grid_y=6, **k))
+    _say(f"atomic mode at the workload's period, {shape}, {T} steps")
+    g = gpu_run(dp, mk(sum_mode=W.SUM_ATOMIC), T, conn=False)
+    o = oracle_run(orc, mk(sum_mode=W.SUM_ORDERED), T)
+    assert len(o["tt"]) > 10000
+    _exact_same(g, o)
     assert g["stats"]["consolidations"] == 1
+
+
+def test_atomic_mode_statistics_ensemble(dp, orc):
+    # past a consolidation the weights are no longer integers: the unordered
+    # mode then sums the currents in another (valid) order than the oracle
+    # and the runs diverge.  Over 16 seeds of the tiny workload with
+    # consolidation every 100 steps: the median per-seed rate deviation
+    # within 1 %, the pooled excitatory-weight histogram (100 bins over
+    # [0, 10]) within L1 0.02, and most rasters differ (the bar the oracle's
+    # two reproducible orders meet against each other)
+    from simref import ensemble_stats
+    N, M, T = 5000, 100, 1000
+    seeds = list(range(1311, 1327))
+    _say(f"atomic mode statistics, {len(seeds)} seeds of tiny, consolidation every 100 steps")
+    ga, go = [], []
+    for seed in seeds:
+        g = gpu_run(dp, W.tiny(seed=seed, sum_mode=W.SUM_ATOMIC, weight_update_period=100), T,
+                    conn=False)
+        o = oracle_run(orc, W.tiny(seed=seed, sum_mode=W.SUM_ORDERED, weight_update_period=100), T)
+        ga.append((len(g["tt"]), (g["tt"], g["ii"]), g["w"]))
+        go.append((len(o["tt"]), (o["tt"], o["ii"]), o["w"]))
+    exc = (np.repeat(np.arange(N), M) % 1250) < 1000
+    med, l1, differ = ensemble_stats(ga, go, exc)
+    _say(f"  median rate deviation {med:.5f}, weight-histogram L1 {l1:.5f}, {differ} rasters differ; "
+         f"ensemble rate ratio {sum(x[0] for x in ga) / sum(x[0] for x in go):.4f}")
+    assert differ >= len(seeds) // 2, differ
+    assert med <= 0.01, med
+    assert l1 <= 0.02, l1
 
 
 def test_counter_invariants(dp):
