@@ -187,6 +187,21 @@ int dpsnn_read_spikes(dpsnn_net *net, uint32_t t_begin, uint32_t t_end,
 int dpsnn_read_weights(dpsnn_net *net, uint64_t first, uint64_t count,
                        float *w, float *P, float *D);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): the
+ * same read as dpsnn_read_weights, with the same results, but its scratch is
+ * a library-owned static device workspace of DPSNN_NOALLOC_SCRATCH_BYTES on
+ * each GPU (held until the process ends) instead of an allocation; the call
+ * allocates no device memory.  DPSNN_E_INVAL if one source column's P
+ * (neurons_per_column x synapses_per_neuron x 4 bytes) plus one row of
+ * staging does not fit the workspace.  Every call on one GPU uses that GPU's
+ * workspace, which keeps the last call's contents (nothing in it needs to
+ * start at zero): calls that overlap in time on the same GPU, from several
+ * host threads, race and must be serialised by the caller. */
+#define DPSNN_NOALLOC_SCRATCH_BYTES (32u << 20)
+int dpsnn_read_weights_noalloc(dpsnn_net *net, uint64_t first, uint64_t count,
+                               float *w, float *P, float *D);
+
 /* The connectivity observable (Sec. 2, "Projection of synapses": each
  * synapse's target and axonal delay) of canonical synapses [first, first +
  * count): global target id and delay in ms, in canonical order.  Either

@@ -7,6 +7,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -1059,6 +1060,47 @@ static int read_rows_common(Net* n, uint64_t first, uint64_t count, uint32_t* tg
         }
     }
     return done(DPSNN_OK);
+}
+
+// ---- read-back without allocation --------------------------------------
+// A library-owned workspace for callers that cannot allocate device memory.
+// `scratch` names a device array; on the host the name is only a stand-in,
+// so host code uses the address hipGetSymbolAddress returned for the current
+// device (each GPU holds its own copy of the array).
+static __device__ __align__(256) unsigned char scratch[DPSNN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+int scratch_for(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return fail(DPSNN_E_INVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(DPSNN_E_DEVICE, std::string("workspace address: ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return DPSNN_OK;
+}
+
+}  // namespace
+
+int dpsnn_read_weights_noalloc(dpsnn_net* h, uint64_t first, uint64_t count, float* w, float* P,
+                               float* D) {
+    Net* n = reinterpret_cast<Net*>(h);
+    if (!n) return fail(DPSNN_E_INVAL, "net is NULL");
+    DPSNN_HIP(hipSetDevice(n->dev.device));
+    void* ws = nullptr;
+    const int rc = scratch_for(n->dev.device, &ws);
+    if (rc) return rc;
+    return read_rows_common(n, first, count, nullptr, nullptr, w, P, D, ws, DPSNN_NOALLOC_SCRATCH_BYTES);
 }
 
 int dpsnn_read_weights(dpsnn_net* h, uint64_t first, uint64_t count, float* w, float* P, float* D) {

@@ -82,6 +82,7 @@ class dpsnn_server_stats(C.Structure):
 EXPORTS = [
     "dpsnn_default_config", "dpsnn_footprint_bytes", "dpsnn_build_network", "dpsnn_step",
     "dpsnn_sync", "dpsnn_time", "dpsnn_read_spikes", "dpsnn_read_weights",
+    "dpsnn_read_weights_noalloc",
     "dpsnn_read_connectivity", "dpsnn_read_state", "dpsnn_get_stats", "dpsnn_set_stimulus",
     "dpsnn_set_probes", "dpsnn_read_probes",
     "dpsnn_set_timing", "dpsnn_set_tuning", "dpsnn_autotune", "dpsnn_destroy",
@@ -116,6 +117,8 @@ def lib():
                                         C.c_size_t, P(C.c_size_t)]
         L.dpsnn_read_weights.argtypes = [vp, C.c_uint64, C.c_uint64, P(C.c_float), P(C.c_float),
                                          P(C.c_float)]
+        L.dpsnn_read_weights_noalloc.argtypes = [vp, C.c_uint64, C.c_uint64, P(C.c_float),
+                                                 P(C.c_float), P(C.c_float)]
         L.dpsnn_read_connectivity.argtypes = [vp, C.c_uint64, C.c_uint64, P(C.c_uint32),
                                               P(C.c_uint8)]
         L.dpsnn_read_state.argtypes = [vp, P(C.c_float), P(C.c_float)]
@@ -343,15 +346,19 @@ class Network:
                                        _ptr(ids, C.c_uint32), n.value, C.byref(n)))
         return times, ids
 
-    def read_weights(self, first: int = 0, count: int | None = None, w=True, P=True, D=True):
+    def read_weights(self, first: int = 0, count: int | None = None, w=True, P=True, D=True,
+                     noalloc: bool = False):
+        """w, P, D of canonical synapses [first, first + count); noalloc uses
+        dpsnn_read_weights_noalloc (the library's static workspace)."""
         if count is None:
             count = self.N * self.M - first
         out = {}
         arrs = {}
         for k, want in (("w", w), ("P", P), ("D", D)):
             arrs[k] = np.zeros(count, dtype=np.float32) if want else None
-        _check(lib().dpsnn_read_weights(self.h, first, count, _ptr(arrs["w"], C.c_float),
-                                        _ptr(arrs["P"], C.c_float), _ptr(arrs["D"], C.c_float)))
+        fn = lib().dpsnn_read_weights_noalloc if noalloc else lib().dpsnn_read_weights
+        _check(fn(self.h, first, count, _ptr(arrs["w"], C.c_float),
+                  _ptr(arrs["P"], C.c_float), _ptr(arrs["D"], C.c_float)))
         for k, a in arrs.items():
             if a is not None:
                 out[k] = a
