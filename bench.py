@@ -513,7 +513,7 @@ def run_window(net, warmup, steps, label):
     return d, wall, first
 
 
-def evolve(net, target, label):
+def evolve(net, target, label, fuse_after=0xFFFFFFFF):
     """Step the network to `target` completed steps (input preparation, not
     timed).  LTP and delivery run as two kernels here, so that the fused
     kernel's launches in a profile of this run are those of the timed window
@@ -526,7 +526,7 @@ def evolve(net, target, label):
         net.step(n)
         net.sync()
         print(f"[bench] {label}: evolved to step {net.t}", file=sys.stderr, flush=True)
-    net.set_tuning(7, 0xFFFFFFFF)
+    net.set_tuning(7, fuse_after)
 
 
 def window_report(cfg, d, wall, steps, first, workload=None, mode=None, measured=False):
@@ -583,7 +583,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="large",
-                    choices=["tiny", "mid", "large", "batched", "serving", "paper"])
+                    choices=["tiny", "mid", "large", "paper128", "batched", "serving", "paper"])
     ap.add_argument("--evolve", type=int, default=None,
                     help="steps the network evolves (untimed) before the warm-up; default 150 "
                          "for large (all-firing from about step 100), 0 otherwise")
@@ -642,10 +642,12 @@ def main():
     n_evolve = args.evolve if args.evolve is not None else (150 if large else 0)
     torch.cuda.set_device(0)
 
+    tune_kv = [tuple(int(x) for x in kv.split("=")) for kv in filter(None, args.tune.split(","))]
+    fuse_after = dict(tune_kv).get(7, 0xFFFFFFFF)
+
     def tuned(net):
-        for kv in filter(None, args.tune.split(",")):
-            k, v = kv.split("=")
-            net.set_tuning(int(k), int(v))
+        for k, v in tune_kv:
+            net.set_tuning(k, v)
         return net
 
     t0 = time.perf_counter()
@@ -668,7 +670,7 @@ def main():
         plain.sync()
         startup["ms_per_step_without_timers"] = 1000.0 * (time.perf_counter() - t1) / args.steps
         plain.close()
-    evolve(net, n_evolve, args.workload)
+    evolve(net, n_evolve, args.workload, fuse_after)
     d, wall, first = run_window(net, args.warmup, args.steps, "timed window")
     head = window_report(cfg, d, wall, args.steps, first, workload=args.workload, mode=args.mode,
                          measured=True)
@@ -691,7 +693,7 @@ def main():
         # rates, timed after its 8 s warm-up (Sec. 3, measurement protocol)
         pcfg = W.paper_table1(7, sum_mode=mode)
         pnet = tuned(dp.Network(pcfg, device=0))
-        evolve(pnet, args.paper_rate_evolve, "paper 128x128")
+        evolve(pnet, args.paper_rate_evolve, "paper 128x128", fuse_after)
         pd_, pwall, pfirst = run_window(pnet, args.warmup, args.paper_rate_steps, "paper 128x128")
         paper_rate = window_report(pcfg, pd_, pwall, args.paper_rate_steps, pfirst)
         paper_rate["config"] = {"workload": _describe("paper Table 1 128x128", pcfg),

@@ -282,6 +282,17 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *   key 10: slots of the partial window (key 2 = 2), 1 .. 13: the own column
  *          first, then the nearest neighbour slots; events to other slots
  *          take global atomics; 0 = automatic (3 / 1)
+ *   key 11: wavefront-level LTP for sparse columns (the spiking neurons of
+ *          a wavefront's raster words gathered into its lanes, their reverse
+ *          rows spread over the lanes a quad at a time, the own column's
+ *          spike history in LDS when key 6 allows): 0 off, 1 on,
+ *          2 = automatic (on / off)
+ *   key 12: wavefront-level delivery for sparse columns (one excitatory
+ *          (source, delay) segment per lane, two inhibitory spikes per
+ *          wavefront at a time, 256-thread workgroups with the key 10 window;
+ *          LTP then also by key 11's body): 0 off, 1 on, 2 = automatic
+ *          (off: measured slower than the run-based path); not used with
+ *          DPSNN_SUM_ORDERED
  * (sparse / dense choice in parentheses) */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 

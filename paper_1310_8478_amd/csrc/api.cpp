@@ -459,6 +459,14 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
             if (value > 13) return fail(DPSNN_E_INVAL, "partial window slots must be 0 (automatic) to 13");
             tn.own_slots = value;
             return DPSNN_OK;
+        case 11:
+            if (value > 2) return fail(DPSNN_E_INVAL, "sparse LTP must be 0 (off), 1 (on) or 2 (automatic)");
+            tn.sparse_ltp = value;
+            return DPSNN_OK;
+        case 12:
+            if (value > 2) return fail(DPSNN_E_INVAL, "sparse delivery must be 0 (off), 1 (on) or 2 (automatic)");
+            tn.sparse_deliver = value;
+            return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");
     }

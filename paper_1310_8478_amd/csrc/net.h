@@ -31,6 +31,8 @@ struct Tuning {
     uint32_t graph = 8;           // steps per captured graph; 0 = every step launched directly
     uint32_t split = 1;           // workgroups sharing a column's full window by slot (1..13)
     uint32_t own_slots = 0;       // slots of the partial window (window 2), 1..13; 0 auto (3 / 1)
+    uint32_t sparse_ltp = 2;      // wavefront-level LTP: 0 off, 1 on, 2 auto (on / off)
+    uint32_t sparse_deliver = 2;  // wavefront-level delivery (and LTP): 0 off, 1 on, 2 auto (off)
     size_t max_lds = 65536;
 };
 

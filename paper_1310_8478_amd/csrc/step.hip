@@ -23,6 +23,9 @@ namespace dpsnn {
 
 namespace {
 
+// entries of the LDS queue of the sparse delivery path (segments or spikes)
+constexpr uint32_t kQueue = 1024;
+
 // ---------------------------------------------------------------------------
 // LTP (item 2.1).  Synapse (p -> k, delay d), post stamp t: the latest spike
 // of p with stamp <= t - d pairs with it, dt = t - d - stamp >= 0 and
@@ -338,7 +341,10 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
     // at 255 (255 also means "never" or "look it up"); staged when the
     // workgroup has enough events to reuse it
     uint8_t* age = lds_raw + win_bytes;
-    const size_t age_bytes = allow_age ? (((size_t)wspan + 15) & ~(size_t)15) : 0;
+    // the age window covers the LDS current window's slots with the partial
+    // window (WIN 2), else every slot this workgroup owns
+    const uint32_t aspan = WIN == 2 ? nlds : wspan;
+    const size_t age_bytes = allow_age ? (((size_t)aspan + 15) & ~(size_t)15) : 0;
     uint32_t* pref = (uint32_t*)(lds_raw + win_bytes + age_bytes);  // [BS + 1]
     uint32_t* pos0 = pref + BS + 1;                      // [BS]
     uint32_t* excf = pos0 + BS;                          // [BS]
@@ -402,7 +408,7 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
             }
         }
         if (ex) {
-            const uint32_t ag = staged ? age[wi - wlo] : 255u;
+            const uint32_t ag = (staged && wi - wlo < aspan) ? age[wi - wlo] : 255u;
             uint32_t dt = 0xFFFFFFFFu;
             if (ag < 255u) {
                 dt = ag + 1u;
@@ -436,8 +442,8 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
         const uint32_t c0 = (uint32_t)((uint64_t)c * d.Ncol * d.M - fb);
         const uint32_t cb = part_bound4(c0, c0 + d.Ncol * d.M, part, nparts);
         const uint32_t total = part_bound4(c0, c0 + d.Ncol * d.M, part + 1u, nparts) - cb;
-        if (allow_age && total >= wspan) {  // block-uniform
-            for (uint32_t x = tid; x < wspan; x += BS) {
+        if (allow_age && total >= aspan) {  // block-uniform
+            for (uint32_t x = tid; x < aspan; x += BS) {
                 const uint32_t xw = x + wlo;
                 const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, xw) : xw / d.Ncol;
                 const int32_t tq = t_last[cmap[sl] * d.Ncol + (xw - sl * d.Ncol)];
@@ -591,8 +597,8 @@ __device__ __forceinline__ void deliver_body(const NetDesc* __restrict__ nds,
                 }
                 uint32_t qlo, qhi;
                 part_slice(Q, part, nparts, qlo, qhi);
-                if (allow_age && !staged && 4u * (qhi - qlo) >= wspan) {  // block-uniform
-                    for (uint32_t x = tid; x < wspan; x += BS) {
+                if (allow_age && !staged && 4u * (qhi - qlo) >= aspan) {  // block-uniform
+                    for (uint32_t x = tid; x < aspan; x += BS) {
                         const uint32_t xw = x + wlo;
                         const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, xw) : xw / d.Ncol;
                         const int32_t tq = t_last[cmap[sl] * d.Ncol + (xw - sl * d.Ncol)];
@@ -714,6 +720,465 @@ __global__ __launch_bounds__(1024) void k_deliver(const NetDesc* __restrict__ nd
                                       tstep, blockIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// Sparse columns: LTP and delivery organised by wavefront.  At the paper's
+// rates a column has a few spiking neurons per stamp, so block-wide run
+// decoding, scans and per-event run searches cost more instructions than the
+// memory traffic they organise.  These paths decode raster words inside one
+// wavefront (no barrier per task) and give every lane a whole piece of work:
+// LTP streams the reverse rows of up to four spiking neurons at once, one
+// aligned quad of entries per lane; delivery queues the excitatory (source,
+// delay) segments of the column in LDS and gives each lane one segment, and
+// streams each inhibitory spike (all of whose synapses have delay 1 and form
+// one range of M synapses) with one wavefront.  The arithmetic and the order
+// in which each synapse's state is updated are those of the dense paths.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+// Row of lane x in a wavefront's batch: the largest lane r with exq[r] <= x
+// (exq: exclusive prefix of the rows' work, ascending over the lanes).
+__device__ __forceinline__ uint32_t wave_find_row(uint32_t exq, uint32_t x) {
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t step = 32; step > 0; step >>= 1) {
+        const uint32_t v = (uint32_t)__shfl((int)exq, (int)(r + step), 64);
+        if (v <= x) r += step;
+    }
+    return r;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)v, o, 64);
+        if (lane >= (uint32_t)o) v += y;
+    }
+    return v;
+}
+
+// Sparse LTP.  Each wavefront collects the spiking neurons of its raster
+// words into its lanes (up to 64 at a time), loads their row bounds at once,
+// and spreads the rows' aligned quads of reverse entries over the lanes, four
+// quads per lane in flight.  With allow_stage the own column's spike history
+// (the source of most incoming synapses) is first copied to LDS when the
+// column's spiking neurons will read it more often than it costs to copy.
+__device__ __forceinline__ void ltp_sparse_body(const NetDesc* __restrict__ nds,
+                                                const uint2* __restrict__ bmap, uint32_t nparts,
+                                                uint32_t allow_stage, uint32_t tstep,
+                                                uint32_t bid) {
+    const uint2 br = bmap[bid / nparts];
+    const uint32_t part = bid % nparts;
+    const NetDesc& nd = nds[br.x];
+    const Dims d = nd.d;
+    const uint32_t t = nd.t0 + tstep;
+    if (t < 1) return;
+    const uint32_t ct = br.y;
+    const uint2* __restrict__ hist = nd.hist;
+    const uint64_t* __restrict__ rowptr = nd.rowptr + (size_t)ct * d.Ncol;
+    // the column's reverse block through pointers offset by its start rounded
+    // down to a multiple of 4: 32-bit offsets, aligned quads
+    const uint64_t rb = rowptr[0] & ~3ull;
+    const uint32_t* __restrict__ rev_srcd = nd.rev_srcd + rb;
+    float* __restrict__ P = nd.Pacc + rb;
+    const float* __restrict__ tp = nd.tp;
+    const uint32_t tp_len = nd.tp_len;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    uint2* hown = (uint2*)lds_raw;  // [Ncol] the own column's spike history
+    __shared__ uint32_t smap[kSlots];
+    __shared__ float tph[64];
+    __shared__ uint32_t nsp_sh;
+    __shared__ unsigned long long red64[16];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t nw = blockDim.x >> 6;
+    const uint64_t* __restrict__ words = nd.ring + ((size_t)(t % d.R) * d.C + ct) * d.W;
+    if (tid < kSlots) smap[tid] = nd.srcmap[ct * kSlots + tid];
+    if (tid < 64) tph[tid] = tid < tp_len ? tp[tid] : 0.0f;
+    if (tid == 0) nsp_sh = 0;
+    __syncthreads();
+    uint32_t cnt_own = 0;
+    for (uint32_t x = tid; x < d.W; x += blockDim.x) cnt_own += (uint32_t)__popcll(words[x]);
+    if (cnt_own) atomicAdd(&nsp_sh, cnt_own);
+    __syncthreads();
+    const uint32_t nsp = nsp_sh;
+    if (nsp == 0) return;  // block-uniform
+    // copying Ncol entries pays when the expected own-column visits (about
+    // M x 0.8 x 0.5 per spiking neuron) outnumber them
+    const bool staged = allow_stage && (uint64_t)nsp * d.M * 2u >= 5ull * d.Ncol;
+    if (staged) {
+        for (uint32_t x = tid; x < d.Ncol; x += blockDim.x) hown[x] = hist[(size_t)ct * d.Ncol + x];
+        __syncthreads();
+    }
+    auto ltp_one = [&](uint32_t sd, float pv) -> float {
+        const uint32_t dl = sd & 63u;
+        const uint32_t sl = sd >> 22;
+        const uint32_t l = (sd >> 6) & 0xFFFFu;
+        const uint2 ht = (staged && sl == 0u) ? hown[l] : hist[smap[sl] * d.Ncol + l];
+        const uint32_t m = ht.x >> dl;
+        uint32_t dt;
+        if (m) {
+            dt = (uint32_t)__ffs((int)m) - 1u;
+        } else {
+            const int32_t to = (int32_t)ht.y;
+            if (to == kNoSpike) return pv;
+            dt = (uint32_t)((int64_t)t - dl - to);
+        }
+        return pv + (dt < 64u ? tph[dt] : (dt < tp_len ? tp[dt] : 0.0f));
+    };
+    const uint32_t gw = wave_uniform(part * nw + (tid >> 6));
+    const uint32_t gstride = nparts * nw;
+    unsigned long long visits = 0;
+    uint32_t wd = gw, wbase = 0;
+    unsigned long long m = 0;
+    for (;;) {
+        // up to 64 spiking neurons of this wavefront's words, one per lane
+        uint32_t cnt = 0, myl = 0;
+        while (cnt < 64u) {
+            if (!m) {
+                if (wd >= d.W) break;
+                m = words[wd];
+                wbase = wd * 64u;
+                wd += gstride;
+                continue;
+            }
+            const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
+            m &= m - 1ull;
+            if (lane == cnt) myl = wbase + b;
+            ++cnt;
+        }
+        if (cnt == 0u) break;
+        uint32_t a = 0, e = 0;
+        if (lane < cnt) {
+            a = (uint32_t)(rowptr[myl] - rb);
+            e = (uint32_t)(rowptr[myl + 1] - rb);
+            visits += e - a;
+        }
+        const uint32_t nq = e > a ? ((e + 3u) >> 2) - (a >> 2) : 0u;
+        const uint32_t inc = wave_incl_scan(nq);
+        const uint32_t exq = inc - nq;
+        const uint32_t Q = (uint32_t)__shfl((int)inc, 63, 64);
+        for (uint32_t base = 0; base < Q; base += 256u) {
+            uint32_t p[4], ra[4], re[4];
+            uint4 sd[4];
+            float4 pv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t x = base + (uint32_t)u * 64u + lane;
+                const uint32_t r = wave_find_row(exq, x);
+                ra[u] = (uint32_t)__shfl((int)a, (int)r, 64);
+                re[u] = (uint32_t)__shfl((int)e, (int)r, 64);
+                const uint32_t rx = (uint32_t)__shfl((int)exq, (int)r, 64);
+                p[u] = ((ra[u] >> 2) + (x - rx)) << 2;
+                if (x >= Q) re[u] = 0u;  // no entry of this quad is in a row
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool any = re[u] != 0u;
+                sd[u] = any ? *(const uint4*)(rev_srcd + p[u]) : make_uint4(0u, 0u, 0u, 0u);
+                pv[u] = any ? *(const float4*)(P + p[u]) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t q = p[u];
+                const bool in0 = q >= ra[u] && q < re[u], in1 = q + 1u >= ra[u] && q + 1u < re[u];
+                const bool in2 = q + 2u >= ra[u] && q + 2u < re[u], in3 = q + 3u >= ra[u] && q + 3u < re[u];
+                float4 o = pv[u];
+                if (in0) o.x = ltp_one(sd[u].x, pv[u].x);
+                if (in1) o.y = ltp_one(sd[u].y, pv[u].y);
+                if (in2) o.z = ltp_one(sd[u].z, pv[u].z);
+                if (in3) o.w = ltp_one(sd[u].w, pv[u].w);
+                // a quad shared with another neuron's row keeps that row's entries
+                if (in0 && in1 && in2 && in3) {
+                    *(float4*)(P + q) = o;
+                } else {
+                    if (in0) P[q] = o.x;
+                    if (in1) P[q + 1] = o.y;
+                    if (in2) P[q + 2] = o.z;
+                    if (in3) P[q + 3] = o.w;
+                }
+            }
+        }
+        if (cnt < 64u) break;  // every word of this wavefront has been read
+    }
+    const unsigned long long v = block_sum64(visits, red64);
+    if (tid == 0 && v) atomicAdd(&nd.stats[ct & 63].ltp_visits, v);
+}
+
+// Sparse delivery.  One pass over the column's (delay, raster word) tasks
+// (two per thread) finds the spiking sources; one block scan gives every
+// excitatory (source, delay) segment and every inhibitory spike a queue slot.
+// Each lane then delivers whole segments, eight synapses (two aligned quads)
+// at a time with all their loads in flight; each wavefront delivers two
+// inhibitory spikes at a time (an inhibitory neuron's M synapses all have
+// delay 1 and lie in one range of the column's delay-1 block).  Currents of
+// the first wslots slots are summed in an LDS window, the rest go to global
+// atomics; LTD reads the own column's spike ages from an LDS copy.
+template <bool FIXED, typename TgtT>
+__device__ __forceinline__ void deliver_sparse_body(const NetDesc* __restrict__ nds,
+                                                    const uint2* __restrict__ bmap,
+                                                    uint32_t nparts, uint32_t wslots,
+                                                    unsigned long long* __restrict__ set_events,
+                                                    uint32_t tstep, uint32_t bid) {
+    const uint2 br = bmap[bid / nparts];
+    const uint32_t part = bid % nparts;
+    const NetDesc& nd = nds[br.x];
+    const Dims d = nd.d;
+    const uint32_t t = nd.t0 + tstep;
+    if (t < 1) return;
+    const uint32_t c = br.y;
+    const uint64_t* __restrict__ ring = nd.ring;
+    const uint64_t* __restrict__ seg_off = nd.seg_off;
+    const uint64_t fb = ((uint64_t)c * d.Ncol * d.M) & ~3ull;
+    const TgtT* __restrict__ tgt = (const TgtT*)nd.tgt + fb;
+    const float* __restrict__ w = nd.w + fb;
+    float* __restrict__ Dacc = nd.Dacc + fb;
+    const int32_t* __restrict__ t_last = nd.t_last;
+    const float* __restrict__ tm = nd.tm;
+    const uint32_t tm_len = nd.tm_len;
+    long long* __restrict__ acc64 = (long long*)nd.acc;
+    float* __restrict__ acc32 = (float*)nd.acc;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ uint32_t cmap[kSlots];
+    __shared__ float tmh[64];
+    __shared__ uint32_t sh[20];
+    __shared__ unsigned long long red64[16];
+    const uint32_t BS = blockDim.x;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t nw = BS >> 6;
+    const uint32_t nlds = wslots * d.Ncol;  // LDS window: the first wslots slots
+    long long* win64 = (long long*)lds_raw;
+    uint8_t* age = lds_raw + (((size_t)nlds * 8 + 15) & ~(size_t)15);         // [Ncol]
+    uint32_t* qa = (uint32_t*)(age + (((size_t)d.Ncol + 15) & ~(size_t)15));  // [kQueue]
+    uint32_t* qe = qa + kQueue;                                                // [kQueue]
+    uint32_t* qi = qe + kQueue;                                                // [kQueue]
+    for (uint32_t x = tid; x < nlds; x += BS) win64[x] = 0;
+    // steps since each own-column neuron's latest spike, 255 = none or older
+    for (uint32_t x = tid; x < d.Ncol; x += BS) {
+        const int32_t tq = t_last[(size_t)c * d.Ncol + x];
+        const int64_t ag = (tq == kNoSpike) ? 255 : (int64_t)t - tq;
+        age[x] = (uint8_t)(ag < 255 ? ag : 255);
+    }
+    if (tid < kSlots) cmap[tid] = nd.colmap[c * kSlots + tid];
+    if (tid < 64) tmh[tid] = tid < tm_len ? tm[tid] : 0.0f;
+    const long long q_inh = to_fixed(d.w_inh);
+    const size_t s1 = (size_t)c * d.segs;
+    const uint32_t inh_lo = d.Ne < d.Ncol ? (uint32_t)(seg_off[s1 + d.Ne] - fb) : 0u;
+    unsigned long long ev_local = 0, exc_events = 0;
+    auto global_id = [&](uint32_t wi) {
+        const uint32_t sl = sizeof(TgtT) == 2 ? div_ncol(d, wi) : wi / d.Ncol;
+        return cmap[sl] * d.Ncol + (wi - sl * d.Ncol);
+    };
+    auto add_current = [&](uint32_t wi, long long q, float f) {
+        if (wi < nlds) {
+            atomicAdd((unsigned long long*)&win64[wi], (unsigned long long)q);
+        } else if (FIXED) {
+            atomicAdd((unsigned long long*)&acc64[global_id(wi)], (unsigned long long)q);
+        } else {
+            atomicAdd(&acc32[global_id(wi)], f);
+        }
+    };
+    // steps dt from the target's latest spike to the arrival (t + 1), or
+    // 0xFFFFFFFF if it never fired; own-column targets from the LDS ages
+    auto arrival_dt = [&](uint32_t wi) -> uint32_t {
+        if (wi < d.Ncol) {
+            const uint32_t ag = age[wi];
+            if (ag < 255u) return ag + 1u;
+        }
+        const int32_t tq = t_last[global_id(wi)];
+        return tq == kNoSpike ? 0xFFFFFFFFu : (uint32_t)((int64_t)t + 1 - tq);
+    };
+    auto ltd_add = [&](uint32_t dt, float dv) -> float {
+        if (dt == 0xFFFFFFFFu) return dv;
+        return dv + (dt < 64u ? tmh[dt] : (dt < tm_len ? tm[dt] : 0.0f));
+    };
+    __syncthreads();
+    // this part's tasks: task index x = part + nparts * k; a round hands two
+    // tasks to each thread
+    const uint32_t ntask = d.Dmax * d.W;
+    const uint32_t nmine = ntask > part ? (ntask - part + nparts - 1u) / nparts : 0u;
+    for (uint32_t k0 = 0; k0 < nmine; k0 += 2u * BS) {
+        unsigned long long mex[2] = {0ull, 0ull}, mih[2] = {0ull, 0ull};
+        uint32_t dd[2] = {1u, 1u}, wd[2] = {0u, 0u};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t k = k0 + (uint32_t)h * BS + tid;
+            if (k >= nmine) continue;
+            const uint32_t x = part + nparts * k;
+            dd[h] = x / d.W + 1u;
+            wd[h] = x - (dd[h] - 1u) * d.W;
+            const int64_t st = (int64_t)t - (int64_t)dd[h] + 1;
+            if (st < 1) continue;
+            const unsigned long long m = ring[((size_t)((uint64_t)st % d.R) * d.C + c) * d.W + wd[h]];
+            // local ids below Ne are excitatory; inhibitory synapses all have delay 1
+            const uint32_t lo = wd[h] * 64u;
+            const unsigned long long em = d.Ne <= lo ? 0ull
+                                         : (d.Ne >= lo + 64u ? ~0ull : ((1ull << (d.Ne - lo)) - 1ull));
+            mex[h] = m & em;
+            mih[h] = dd[h] == 1u ? (m & ~em) : 0ull;
+        }
+        const uint32_t nex = (uint32_t)(__popcll(mex[0]) + __popcll(mex[1]));
+        const uint32_t nih = (uint32_t)(__popcll(mih[0]) + __popcll(mih[1]));
+        uint32_t tot;
+        // at most 2 x 64 bits per thread and 256 threads: each half < 2^16
+        const uint32_t pre = block_scan(nex | (nih << 16), sh, tot);
+        const uint32_t tex = tot & 0xFFFFu, tih = tot >> 16;
+        for (uint32_t r0 = 0; r0 < max(tex, tih); r0 += kQueue) {
+            // queue slots [r0, r0 + kQueue) of both kinds
+            uint32_t ie = pre & 0xFFFFu, ii = pre >> 16;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                unsigned long long me = mex[h], mi = mih[h];
+                while (me) {
+                    const uint32_t b = (uint32_t)__ffsll((long long)me) - 1u;
+                    me &= me - 1ull;
+                    if (ie >= r0 && ie < r0 + kQueue) {
+                        const size_t sg = s1 + (size_t)(dd[h] - 1u) * d.Ncol + wd[h] * 64u + b;
+                        qa[ie - r0] = (uint32_t)(seg_off[sg] - fb);
+                        qe[ie - r0] = (uint32_t)(seg_off[sg + 1] - fb);
+                    }
+                    ++ie;
+                }
+                while (mi) {
+                    const uint32_t b = (uint32_t)__ffsll((long long)mi) - 1u;
+                    mi &= mi - 1ull;
+                    if (ii >= r0 && ii < r0 + kQueue) qi[ii - r0] = wd[h] * 64u + b;
+                    ++ii;
+                }
+            }
+            __syncthreads();
+            const uint32_t ne = tex > r0 ? min(kQueue, tex - r0) : 0u;
+            const uint32_t ni = tih > r0 ? min(kQueue, tih - r0) : 0u;
+            // excitatory segments: one per lane, two aligned quads at a time
+            for (uint32_t sgi = tid; sgi < ne; sgi += BS) {
+                const uint32_t a = qa[sgi], e = qe[sgi];
+                for (uint32_t p0 = a & ~3u; p0 < e; p0 += 8u) {
+                    uint32_t wi[8];
+                    float wv[8], dv[8];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const uint32_t q = p0 + 4u * (uint32_t)u;
+                        const bool ok = q < e;
+                        if (sizeof(TgtT) == 2) {
+                            const uint2 tv = ok ? *(const uint2*)(tgt + q) : make_uint2(0u, 0u);
+                            wi[4 * u + 0] = tv.x & 0xFFFFu; wi[4 * u + 1] = tv.x >> 16;
+                            wi[4 * u + 2] = tv.y & 0xFFFFu; wi[4 * u + 3] = tv.y >> 16;
+                        } else {
+                            const uint4 tv = ok ? *(const uint4*)((const uint32_t*)tgt + q)
+                                                : make_uint4(0u, 0u, 0u, 0u);
+                            wi[4 * u + 0] = tv.x; wi[4 * u + 1] = tv.y;
+                            wi[4 * u + 2] = tv.z; wi[4 * u + 3] = tv.w;
+                        }
+                        const float4 w4 = ok ? *(const float4*)(w + q) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        const float4 d4 = ok ? *(const float4*)(Dacc + q) : make_float4(0.f, 0.f, 0.f, 0.f);
+                        wv[4 * u + 0] = w4.x; wv[4 * u + 1] = w4.y; wv[4 * u + 2] = w4.z; wv[4 * u + 3] = w4.w;
+                        dv[4 * u + 0] = d4.x; dv[4 * u + 1] = d4.y; dv[4 * u + 2] = d4.z; dv[4 * u + 3] = d4.w;
+                    }
+                    uint32_t dts[8];
+                    bool in[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const uint32_t pj = p0 + (uint32_t)j;
+                        in[j] = pj >= a && pj < e;
+                        dts[j] = in[j] ? arrival_dt(wi[j]) : 0xFFFFFFFFu;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        if (!in[j]) continue;
+                        add_current(wi[j], to_fixed(wv[j]), wv[j]);
+                        dv[j] = ltd_add(dts[j], dv[j]);
+                    }
+                    // a quad shared with another segment keeps that segment's D
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const uint32_t q = p0 + 4u * (uint32_t)u;
+                        if (in[4 * u] && in[4 * u + 1] && in[4 * u + 2] && in[4 * u + 3]) {
+                            *(float4*)(Dacc + q) = make_float4(dv[4 * u], dv[4 * u + 1], dv[4 * u + 2], dv[4 * u + 3]);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < 4; ++j)
+                                if (in[4 * u + j]) Dacc[q + j] = dv[4 * u + j];
+                        }
+                    }
+                }
+                ev_local += e - a;
+                exc_events += e - a;
+            }
+            // inhibitory spikes: two per wavefront at a time, one quad per lane each
+            for (uint32_t sp = tid >> 6; sp < ni; sp += 2u * nw) {
+                const uint32_t sp2 = sp + nw;
+                const uint32_t a1 = inh_lo + (qi[sp] - d.Ne) * d.M;
+                const uint32_t a2 = sp2 < ni ? inh_lo + (qi[sp2] - d.Ne) * d.M : a1;
+                const uint32_t n2 = sp2 < ni ? d.M : 0u;
+                for (uint32_t off = 4u * lane; off < d.M + 3u; off += 256u) {
+                    uint32_t wi[8];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const uint32_t q = ((u == 0 ? a1 : a2) & ~3u) + off;
+                        const bool ok = q < (u == 0 ? a1 + d.M : a2 + n2);
+                        if (sizeof(TgtT) == 2) {
+                            const uint2 tv = ok ? *(const uint2*)(tgt + q) : make_uint2(0u, 0u);
+                            wi[4 * u + 0] = tv.x & 0xFFFFu; wi[4 * u + 1] = tv.x >> 16;
+                            wi[4 * u + 2] = tv.y & 0xFFFFu; wi[4 * u + 3] = tv.y >> 16;
+                        } else {
+                            const uint4 tv = ok ? *(const uint4*)((const uint32_t*)tgt + q)
+                                                : make_uint4(0u, 0u, 0u, 0u);
+                            wi[4 * u + 0] = tv.x; wi[4 * u + 1] = tv.y;
+                            wi[4 * u + 2] = tv.z; wi[4 * u + 3] = tv.w;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const uint32_t sa = u == 0 ? a1 : a2, se = u == 0 ? a1 + d.M : a2 + n2;
+                        const uint32_t q = (sa & ~3u) + off;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (q + (uint32_t)j >= sa && q + (uint32_t)j < se)
+                                add_current(wi[4 * u + j], q_inh, d.w_inh);
+                    }
+                }
+                if (lane == 0) ev_local += d.M + n2;
+            }
+            __syncthreads();  // the queues are refilled
+        }
+    }
+    // flush the window: one global atomic per target that received current
+    for (uint32_t x = tid; x < nlds; x += BS) {
+        const long long val = win64[x];
+        if (val != 0) {
+            const uint32_t kg = global_id(x);
+            if (FIXED) atomicAdd((unsigned long long*)&acc64[kg], (unsigned long long)val);
+            else atomicAdd(&acc32[kg], from_fixed(val));
+        }
+    }
+    const unsigned long long events = block_sum64(ev_local, red64);
+    const unsigned long long exc_total = block_sum64(exc_events, red64);
+    if (tid == 0 && events) {
+        atomicAdd(&nd.stats[c & 63].events, events);
+        atomicAdd(&nd.stats[c & 63].events_exc, exc_total);
+        atomicAdd(set_events, events);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ltp_sp(const NetDesc* __restrict__ nds,
+                                                const uint2* __restrict__ bmap, uint32_t nparts,
+                                                uint32_t allow_stage, uint32_t tstep) {
+    ltp_sparse_body(nds, bmap, nparts, allow_stage, tstep, blockIdx.x);
+}
+
+template <bool FIXED, typename TgtT>
+__global__ __launch_bounds__(256) void k_deliver_sp(const NetDesc* __restrict__ nds,
+                                                    const uint2* __restrict__ bmap,
+                                                    uint32_t nparts, uint32_t wslots,
+                                                    unsigned long long* __restrict__ set_events,
+                                                    uint32_t tstep) {
+    deliver_sparse_body<FIXED, TgtT>(nds, bmap, nparts, wslots, set_events, tstep, blockIdx.x);
+}
+
 // LTP and delivery of one step in a single launch, for launches small enough
 // that kernel boundaries dominate: the first n_ltp workgroups run LTP, the
 // rest delivery.  The two write disjoint state (P; currents and D) and read
@@ -725,12 +1190,30 @@ __global__ __launch_bounds__(1024) void k_ltp_deliver(const NetDesc* __restrict_
                                                       uint32_t nparts, uint32_t nsplit,
                                                       uint32_t wslots,
                                                       unsigned long long* __restrict__ set_events,
-                                                      uint32_t tstep, uint32_t n_ltp) {
-    if (blockIdx.x < n_ltp)
+                                                      uint32_t tstep, uint32_t n_ltp,
+                                                      uint32_t ltp_sparse) {
+    if (blockIdx.x < n_ltp && ltp_sparse)
+        ltp_sparse_body(nds, bmap, nparts, allow_stage, tstep, blockIdx.x);
+    else if (blockIdx.x < n_ltp)
         ltp_body<4>(nds, bmap, allow_stage, nparts, tstep, blockIdx.x);
     else
         deliver_body<FIXED, WIN, TgtT, U>(nds, bmap, allow_age, nparts, nsplit, wslots, set_events,
                                           tstep, blockIdx.x - n_ltp);
+}
+
+// Both sparse paths in one launch: the first n_ltp workgroups do LTP.
+template <bool FIXED, typename TgtT>
+__global__ __launch_bounds__(256) void k_ltp_deliver_sp(const NetDesc* __restrict__ nds,
+                                                        const uint2* __restrict__ bmap,
+                                                        uint32_t nparts, uint32_t wslots,
+                                                        uint32_t allow_stage,
+                                                        unsigned long long* __restrict__ set_events,
+                                                        uint32_t tstep, uint32_t n_ltp) {
+    if (blockIdx.x < n_ltp)
+        ltp_sparse_body(nds, bmap, nparts, allow_stage, tstep, blockIdx.x);
+    else
+        deliver_sparse_body<FIXED, TgtT>(nds, bmap, nparts, wslots, set_events, tstep,
+                                         blockIdx.x - n_ltp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1215,6 +1698,7 @@ struct FusedLtp {
     bool on = false;
     uint32_t allow_stage = 0;
     size_t lds = 0;
+    uint32_t sparse = 0;   // LTP by the wavefront-level sparse body
 };
 
 template <typename TgtT>
@@ -1250,7 +1734,8 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
     if (tune.window == 1 && win_full + base + 256 <= tune.max_lds) wmode = 1;
     else if (tune.window >= 1 && win_own + base + 256 <= tune.max_lds) wmode = 2;
     const uint32_t nsplit = wmode == 1 ? split_req : 1u;
-    const size_t agew = (((size_t)(wmode == 1 ? share : (uint32_t)kSlots) * L.max_ncol) + 15) & ~(size_t)15;
+    const size_t agew = (((size_t)(wmode == 1 ? share : (wmode == 2 ? wslots : (uint32_t)kSlots)) *
+                          L.max_ncol) + 15) & ~(size_t)15;
     const size_t lds0 = (wmode == 1 ? win_full : (wmode == 2 ? win_own : 0)) + base;
     const uint32_t allow_age = (tune.age && lds0 + agew + 256 <= tune.max_lds) ? 1u : 0u;
     const size_t lds = lds0 + (allow_age ? agew : 0);
@@ -1263,7 +1748,7 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
             allow_lds(k_ltp_deliver<FX, WN, TgtT, UU>, lf);                                    \
             hipLaunchKernelGGL((k_ltp_deliver<FX, WN, TgtT, UU>), dim3(n_ltp + nblk), dim3(BS),  \
                                lf, stream, L.descs, L.bmap_col, fl.allow_stage, allow_age,     \
-                               nparts, nsplit, wslots, L.ev_count, tstep, n_ltp);              \
+                               nparts, nsplit, wslots, L.ev_count, tstep, n_ltp, fl.sparse);   \
         } else {                                                                               \
             allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                       \
             hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(nblk), dim3(BS), lds,       \
@@ -1288,6 +1773,61 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
     }
 #undef DPSNN_DELIVER_W
 #undef DPSNN_DELIVER
+    return hipGetLastError();
+}
+
+// The wavefront-level sparse paths (LTP and delivery; FIXED or ATOMIC
+// summation), fused into one launch when the fuse rule allows.
+template <typename TgtT>
+hipError_t launch_sparse(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
+                         uint32_t nparts, uint32_t tstep) {
+    const bool fixed = L.sum_mode == DPSNN_SUM_FIXED;
+    auto pad16 = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    // delivery: the LDS window over the first wslots slots (fewer if it does
+    // not fit), the own column's spike ages and three queues
+    uint32_t wslots = std::min<uint32_t>(std::max<uint32_t>(tune.own_slots, 1u), (uint32_t)kSlots);
+    auto lds_for = [&](uint32_t ws) {
+        return pad16((size_t)ws * L.max_ncol * 8) + pad16(L.max_ncol) + 3 * sizeof(uint32_t) * kQueue;
+    };
+    while (wslots > 0 && lds_for(wslots) + 2048 > tune.max_lds) --wslots;
+    const size_t lds_d = lds_for(wslots);
+    // LTP: the own column's spike history (8 bytes per neuron) when it fits
+    const size_t hist_b = (size_t)L.max_ncol * 8;
+    const uint32_t allow_stage = (tune.ltp_stage && hist_b <= 32768 && hist_b + 2048 <= tune.max_lds) ? 1u : 0u;
+    const size_t lds_l = allow_stage ? hist_b : 0;
+    const uint32_t n = L.n_col * nparts;
+    if ((uint64_t)n <= tune.fuse) {
+        const size_t lds = std::max(lds_d, lds_l);
+        tm.begin(1, stream);
+        if (fixed) {
+            allow_lds(k_ltp_deliver_sp<true, TgtT>, lds);
+            hipLaunchKernelGGL((k_ltp_deliver_sp<true, TgtT>), dim3(2 * n), dim3(256), lds, stream,
+                               L.descs, L.bmap_col, nparts, wslots, allow_stage, L.ev_count, tstep, n);
+        } else {
+            allow_lds(k_ltp_deliver_sp<false, TgtT>, lds);
+            hipLaunchKernelGGL((k_ltp_deliver_sp<false, TgtT>), dim3(2 * n), dim3(256), lds, stream,
+                               L.descs, L.bmap_col, nparts, wslots, allow_stage, L.ev_count, tstep, n);
+        }
+        tm.end(stream);
+        return hipGetLastError();
+    }
+    tm.begin(0, stream);
+    hipLaunchKernelGGL(k_ltp_sp, dim3(n), dim3(256), lds_l, stream, L.descs, L.bmap_col, nparts,
+                       allow_stage, tstep);
+    tm.end(stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    tm.begin(1, stream);
+    if (fixed) {
+        allow_lds(k_deliver_sp<true, TgtT>, lds_d);
+        hipLaunchKernelGGL((k_deliver_sp<true, TgtT>), dim3(n), dim3(256), lds_d, stream, L.descs,
+                           L.bmap_col, nparts, wslots, L.ev_count, tstep);
+    } else {
+        allow_lds(k_deliver_sp<false, TgtT>, lds_d);
+        hipLaunchKernelGGL((k_deliver_sp<false, TgtT>), dim3(n), dim3(256), lds_d, stream, L.descs,
+                           L.bmap_col, nparts, wslots, L.ev_count, tstep);
+    }
+    tm.end(stream);
     return hipGetLastError();
 }
 
@@ -1399,6 +1939,8 @@ Tuning effective_tuning(const LaunchSet& L, const Tuning& tune) {
     // the partial window: the own column alone on grids below 2048 columns,
     // the own column and two neighbour slots on larger ones (measured)
     if (t.own_slots == 0u) t.own_slots = (sparse && L.n_col >= 2048u) ? 3u : 1u;
+    if (t.sparse_ltp == 2u) t.sparse_ltp = sparse ? 1u : 0u;
+    if (t.sparse_deliver == 2u) t.sparse_deliver = 0u;  // measured slower than the run path
     return t;
 }
 
@@ -1408,6 +1950,7 @@ bool same_shapes(const Tuning& a, const Tuning& b) {
     return a.deliver_block == b.deliver_block && a.ltp_block == b.ltp_block && a.window == b.window &&
            a.unroll == b.unroll && a.age == b.age && a.parts == b.parts && a.ltp_stage == b.ltp_stage &&
            a.fuse == b.fuse && a.split == b.split && a.own_slots == b.own_slots &&
+           a.sparse_ltp == b.sparse_ltp && a.sparse_deliver == b.sparse_deliver &&
            a.max_lds == b.max_lds;
 }
 
@@ -1419,21 +1962,43 @@ bool same_shapes(const Tuning& a, const Tuning& b) {
 hipError_t enqueue_step(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_t stream,
                         Net* const* members, uint32_t tstep, bool any_spikes, const uint8_t* wu) {
     hipError_t e;
-    if (any_spikes) {
-        const uint32_t BS = std::max<uint32_t>(tune.ltp_block, ((L.max_w + 63) / 64) * 64);
-        const size_t base = ((size_t)2 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
-        const size_t hw = (size_t)kSlots * L.max_ncol * sizeof(uint32_t);
-        const uint32_t allow = (tune.ltp_stage && base + hw <= tune.max_lds) ? 1u : 0u;
-        const size_t lds = base + (allow ? hw : 0);
+    if (any_spikes && tune.sparse_deliver && L.sum_mode != DPSNN_SUM_ORDERED) {
+        const uint32_t nparts = column_parts(L, tune);
+        e = L.tgt16 ? launch_sparse<uint16_t>(L, tune, tm, stream, nparts, tstep)
+                    : launch_sparse<uint32_t>(L, tune, tm, stream, nparts, tstep);
+        if (e != hipSuccess) return e;
+    } else if (any_spikes) {
+        const uint32_t BSd = std::max<uint32_t>(tune.deliver_block, ((L.max_w + 63) / 64) * 64);
+        const bool ltp_sp = tune.sparse_ltp != 0u;
+        const uint32_t BS = ltp_sp ? BSd : std::max<uint32_t>(tune.ltp_block, ((L.max_w + 63) / 64) * 64);
+        size_t lds;
+        uint32_t allow;
+        if (ltp_sp) {
+            // the sparse LTP body stages the own column's spike history
+            const size_t hist_b = (size_t)L.max_ncol * 8;
+            allow = (tune.ltp_stage && hist_b <= 32768 && hist_b + 2048 <= tune.max_lds) ? 1u : 0u;
+            lds = allow ? hist_b : 0;
+        } else {
+            const size_t base = ((size_t)2 * BS + 1 + 20 + 16 + 64) * sizeof(uint32_t);
+            const size_t hw = (size_t)kSlots * L.max_ncol * sizeof(uint32_t);
+            allow = (tune.ltp_stage && base + hw <= tune.max_lds) ? 1u : 0u;
+            lds = base + (allow ? hw : 0);
+        }
         const uint32_t nparts = column_parts(L, tune);
         // small launches run LTP and delivery as one kernel (same workgroup size)
         FusedLtp fl;
-        const uint32_t BSd = std::max<uint32_t>(tune.deliver_block, ((L.max_w + 63) / 64) * 64);
         fl.on = L.sum_mode != DPSNN_SUM_ORDERED && BSd == BS &&
                 (uint64_t)L.n_col * nparts <= tune.fuse;
         fl.allow_stage = allow;
         fl.lds = lds;
-        if (!fl.on) {
+        fl.sparse = ltp_sp ? 1u : 0u;
+        if (!fl.on && ltp_sp) {
+            tm.begin(0, stream);
+            hipLaunchKernelGGL(k_ltp_sp, dim3(L.n_col * nparts), dim3(256), lds, stream, L.descs,
+                               L.bmap_col, nparts, allow, tstep);
+            tm.end(stream);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        } else if (!fl.on) {
             allow_lds(k_ltp<4>, lds);
             tm.begin(0, stream);
             hipLaunchKernelGGL(k_ltp<4>, dim3(L.n_col * nparts), dim3(BS), lds, stream, L.descs,

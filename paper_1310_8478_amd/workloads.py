@@ -117,10 +117,17 @@ def paper_table3(k: int, **over) -> dict:
     return paper_shaped(grid=(gx, gy), M=M, neurons_per_column=ncol, **base)
 
 
+def paper128(**over) -> dict:
+    """Table 1's 128x128 grid of 1000-neuron columns (3.28 G synapses), the
+    paper's largest single-run analogue of the 3.2 G-synapse network."""
+    return paper_table1(7, **over)
+
+
 WORKLOADS = {
     "tiny": (tiny, 1000),
     "mid": (mid, 1000),
     "large": (large, 1000),
+    "paper128": (paper128, 10000),
 }
 
 

@@ -99,3 +99,23 @@ def test_silent_network_and_stimulus(dp, orc, mode):
     o = oracle_run(orc, cfg, T, stim=(t, ids, mv))
     assert_bitexact(g, o)
     assert len(o["tt"]) >= 4
+
+
+@pytest.mark.parametrize("name", list(EDGE))
+def test_edge_configuration_sparse_path_bitexact(dp, orc, name):
+    # the wavefront-level sparse LTP and delivery paths forced on, on every
+    # degenerate shape (queue rounds, 32-bit targets, no LDS window for the
+    # widest column, inhibitory fan-out beyond one pass of a wavefront)
+    cfg, T = EDGE[name]
+    cfg = dict(cfg, sum_mode=W.SUM_FIXED)
+    _say(f"edge {name}, sparse paths, {T} steps")
+    o = oracle_run(orc, cfg, T)
+    g = gpu_run(dp, cfg, T, tuning=((12, 1),))
+    assert_bitexact(g, o)
+    assert g["stats"]["events"] == o["counters"]["events"]
+    assert g["stats"]["ltp_visits"] == o["counters"]["ltp_visits"]
+    # the sparse LTP beside the run-based delivery, with the partial-window ages
+    g = gpu_run(dp, cfg, T, tuning=((11, 1), (2, 2), (4, 1)))
+    assert_bitexact(g, o)
+    assert g["stats"]["events"] == o["counters"]["events"]
+    assert g["stats"]["ltp_visits"] == o["counters"]["ltp_visits"]

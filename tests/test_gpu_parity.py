@@ -209,6 +209,10 @@ TUNINGS = [
     ((9, 2), (2, 1)), ((9, 3), (2, 1), (4, 1), (0, 512), (1, 512)), ((9, 13), (2, 1), (5, 2)),
     ((9, 2), (2, 1), (7, 0), (3, 1)),
     ((2, 2), (10, 5)), ((2, 2), (10, 13), (0, 256), (1, 256)), ((2, 2), (10, 3), (4, 1), (7, 0)),
+    # the wavefront-level sparse paths, forced on
+    ((12, 1),), ((12, 1), (10, 3)), ((12, 1), (10, 13)), ((12, 1), (5, 3)), ((12, 1), (7, 0)),
+    ((12, 1), (10, 1), (5, 2), (7, 0)), ((11, 1),), ((11, 1), (7, 0)), ((11, 1), (6, 0), (5, 3)),
+    ((11, 1), (2, 2), (4, 1), (10, 3)), ((11, 1), (0, 1024), (4, 1)),
 ]
 
 
@@ -221,7 +225,8 @@ def test_dense_regime_column_parts(dp):
     ref = gpu_run(dp, cfg, T, tuning=((5, 1),), conn=False)
     assert (np.bincount(ref["tt"], minlength=T + 1)[110:] == 2500).sum() >= 20
     for tn in (((5, 13),), ((5, 200),), ((5, 9), (2, 2), (6, 0)), ((9, 2), (2, 1)),
-               ((9, 5), (2, 1), (5, 3), (4, 1))):
+               ((9, 5), (2, 1), (5, 3), (4, 1)), ((12, 1),), ((12, 1), (5, 13), (10, 2)),
+               ((12, 1), (7, 0), (10, 13)), ((11, 1),), ((11, 1), (2, 2), (4, 1), (5, 7))):
         g = gpu_run(dp, cfg, T, tuning=tn, conn=False)
         assert_bitexact(g, ref, conn=False)
         assert g["stats"]["events"] == ref["stats"]["events"]
@@ -269,7 +274,7 @@ def _exact_same(g, o):
         np.testing.assert_array_equal(bits(g[k]), bits(o[k]), err_msg=k)
 
 
-@pytest.mark.parametrize("shape", ["tiny", "mid_6x6"])
+@pytest.mark.parametrize("shape", ["tiny", "mid_6x6", "tiny_sparse_path"])
 def test_atomic_mode_exact_at_the_workload_period(dp, orc, shape):
     # the workloads consolidate every 1000 steps, so over their 1000-step
     # runs every weight is 6 or -5 and the thalamic input 20 mV: every
@@ -277,9 +282,10 @@ def test_atomic_mode_exact_at_the_workload_period(dp, orc, shape):
     # the unordered mode reproduces the oracle bit for bit (rate ratio 1,
     # weight-histogram L1 0), the consolidation at the last step included
     T = 1000
-    mk = W.tiny if shape == "tiny" else (lambda **k: W.mid(grid_x=6, grid_y=6, **k))
+    mk = (lambda **k: W.mid(grid_x=6, grid_y=6, **k)) if shape == "mid_6x6" else W.tiny
+    tuning = ((12, 1),) if shape == "tiny_sparse_path" else ()
     _say(f"atomic mode at the workload's period, {shape}, {T} steps")
-    g = gpu_run(dp, mk(sum_mode=W.SUM_ATOMIC), T, conn=False)
+    g = gpu_run(dp, mk(sum_mode=W.SUM_ATOMIC), T, tuning=tuning, conn=False)
     o = oracle_run(orc, mk(sum_mode=W.SUM_ORDERED), T)
     assert len(o["tt"]) > 10000
     _exact_same(g, o)
@@ -356,7 +362,7 @@ def test_tuning_and_step_arguments(dp):
     net = dp.Network(W.tiny(weight_update_period=40))
     try:
         for key, val in ((0, 300), (1, 100), (2, 4), (3, 3), (4, 3), (5, 1025), (6, 3),
-                         (8, 1025), (9, 0), (9, 14), (10, 14), (11, 1)):
+                         (8, 1025), (9, 0), (9, 14), (10, 14), (11, 3), (12, 3), (13, 1)):
             with pytest.raises(dp.DpsnnError) as e:
                 net.set_tuning(key, val)
             assert e.value.code == dp.E_INVAL, (key, val)
