@@ -293,6 +293,10 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *          LTP then also by key 11's body): 0 off, 1 on, 2 = automatic
  *          (off: measured slower than the run-based path); not used with
  *          DPSNN_SUM_ORDERED
+ *   key 13: target columns per workgroup of the key 11 LTP, 1 .. 8, for
+ *          single networks with unsplit columns (key 5): a workgroup's time is
+ *          set by its chain of dependent loads more than by its work, so
+ *          fewer workgroups with more columns finish sooner; 0 = automatic
  * (sparse / dense choice in parentheses) */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 

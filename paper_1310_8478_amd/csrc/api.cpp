@@ -467,6 +467,10 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
             if (value > 2) return fail(DPSNN_E_INVAL, "sparse delivery must be 0 (off), 1 (on) or 2 (automatic)");
             tn.sparse_deliver = value;
             return DPSNN_OK;
+        case 13:
+            if (value > 8) return fail(DPSNN_E_INVAL, "columns per sparse LTP workgroup must be 0 (automatic) to 8");
+            tn.ltp_cols = value;
+            return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");
     }

@@ -33,6 +33,7 @@ struct Tuning {
     uint32_t own_slots = 0;       // slots of the partial window (window 2), 1..13; 0 auto (3 / 1)
     uint32_t sparse_ltp = 2;      // wavefront-level LTP: 0 off, 1 on, 2 auto (on / off)
     uint32_t sparse_deliver = 2;  // wavefront-level delivery (and LTP): 0 off, 1 on, 2 auto (off)
+    uint32_t ltp_cols = 0;        // target columns per sparse LTP workgroup, 1..8; 0 auto
     size_t max_lds = 65536;
 };
 

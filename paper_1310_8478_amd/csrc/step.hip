@@ -763,61 +763,74 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 // Sparse LTP.  Each wavefront collects the spiking neurons of its raster
 // words into its lanes (up to 64 at a time), loads their row bounds at once,
 // and spreads the rows' aligned quads of reverse entries over the lanes, four
-// quads per lane in flight.  With allow_stage the own column's spike history
-// (the source of most incoming synapses) is first copied to LDS when the
-// column's spiking neurons will read it more often than it costs to copy.
+// quads per lane in flight.  A workgroup takes `cpw` target columns of one
+// network (map entries bid, bid + nwg, ...: with nwg a multiple of 8 they sit
+// on the workgroup's XCD), or with cpw = 1 one part of one column of any
+// network of the set; its latency is that of its longest chain of loads, not
+// of its column count, so fewer, fuller workgroups finish sooner.  With
+// allow_stage and cpw = 1 the own column's spike history (the source of most
+// incoming synapses) is first copied to LDS when the column's spiking
+// neurons will read it more often than the copy costs.
+constexpr uint32_t kMaxCpw = 8;
+
 __device__ __forceinline__ void ltp_sparse_body(const NetDesc* __restrict__ nds,
                                                 const uint2* __restrict__ bmap, uint32_t nparts,
-                                                uint32_t allow_stage, uint32_t tstep,
+                                                uint32_t allow_stage, uint32_t cpw, uint32_t nwg,
+                                                uint32_t n_entries, uint32_t tstep,
                                                 uint32_t bid) {
-    const uint2 br = bmap[bid / nparts];
-    const uint32_t part = bid % nparts;
-    const NetDesc& nd = nds[br.x];
+    const uint32_t part = cpw == 1u ? bid % nparts : 0u;
+    const uint32_t e0 = cpw == 1u ? bid / nparts : bid;
+    if (e0 >= n_entries) return;  // a workgroup beyond the columns (nwg is rounded up)
+    const NetDesc& nd = nds[bmap[e0].x];  // cpw > 1: one network
     const Dims d = nd.d;
     const uint32_t t = nd.t0 + tstep;
     if (t < 1) return;
-    const uint32_t ct = br.y;
     const uint2* __restrict__ hist = nd.hist;
-    const uint64_t* __restrict__ rowptr = nd.rowptr + (size_t)ct * d.Ncol;
-    // the column's reverse block through pointers offset by its start rounded
-    // down to a multiple of 4: 32-bit offsets, aligned quads
-    const uint64_t rb = rowptr[0] & ~3ull;
-    const uint32_t* __restrict__ rev_srcd = nd.rev_srcd + rb;
-    float* __restrict__ P = nd.Pacc + rb;
+    const uint64_t* __restrict__ rowptr = nd.rowptr;
+    const uint32_t* __restrict__ rev_srcd = nd.rev_srcd;
+    float* __restrict__ P = nd.Pacc;
     const float* __restrict__ tp = nd.tp;
     const uint32_t tp_len = nd.tp_len;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    uint2* hown = (uint2*)lds_raw;  // [Ncol] the own column's spike history
-    __shared__ uint32_t smap[kSlots];
+    uint2* hown = (uint2*)lds_raw;  // [Ncol] the own column's spike history (cpw = 1)
+    __shared__ uint32_t smap[kMaxCpw * kSlots];
+    __shared__ uint32_t ccol[kMaxCpw];
     __shared__ float tph[64];
     __shared__ uint32_t nsp_sh;
     __shared__ unsigned long long red64[16];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = lane_id();
     const uint32_t nw = blockDim.x >> 6;
-    const uint64_t* __restrict__ words = nd.ring + ((size_t)(t % d.R) * d.C + ct) * d.W;
-    if (tid < kSlots) smap[tid] = nd.srcmap[ct * kSlots + tid];
+    // this workgroup's columns: entries e0 + k * nwg below n_entries (cpw = 1: e0)
+    const uint32_t ncols = cpw == 1u ? 1u : min(cpw, (n_entries - e0 + nwg - 1u) / nwg);
+    if (tid < ncols) ccol[tid] = bmap[e0 + tid * nwg].y;
     if (tid < 64) tph[tid] = tid < tp_len ? tp[tid] : 0.0f;
     if (tid == 0) nsp_sh = 0;
     __syncthreads();
+    for (uint32_t x = tid; x < ncols * kSlots; x += blockDim.x)
+        smap[x] = nd.srcmap[ccol[x / kSlots] * kSlots + (x % kSlots)];
+    const uint64_t* __restrict__ ring = nd.ring + (size_t)(t % d.R) * d.C * d.W;
+    const uint32_t nwords = ncols * d.W;
     uint32_t cnt_own = 0;
-    for (uint32_t x = tid; x < d.W; x += blockDim.x) cnt_own += (uint32_t)__popcll(words[x]);
+    for (uint32_t x = tid; x < nwords; x += blockDim.x)
+        cnt_own += (uint32_t)__popcll(ring[(size_t)ccol[x / d.W] * d.W + (x % d.W)]);
     if (cnt_own) atomicAdd(&nsp_sh, cnt_own);
     __syncthreads();
     const uint32_t nsp = nsp_sh;
     if (nsp == 0) return;  // block-uniform
     // copying Ncol entries pays when the expected own-column visits (about
     // M x 0.8 x 0.5 per spiking neuron) outnumber them
-    const bool staged = allow_stage && (uint64_t)nsp * d.M * 2u >= 5ull * d.Ncol;
+    const bool staged = cpw == 1u && allow_stage && (uint64_t)nsp * d.M * 2u >= 5ull * d.Ncol;
     if (staged) {
-        for (uint32_t x = tid; x < d.Ncol; x += blockDim.x) hown[x] = hist[(size_t)ct * d.Ncol + x];
+        for (uint32_t x = tid; x < d.Ncol; x += blockDim.x) hown[x] = hist[(size_t)ccol[0] * d.Ncol + x];
         __syncthreads();
     }
-    auto ltp_one = [&](uint32_t sd, float pv) -> float {
+    // LTP of one reverse entry of a target in the workgroup's column k
+    auto ltp_one = [&](uint32_t k, uint32_t sd, float pv) -> float {
         const uint32_t dl = sd & 63u;
         const uint32_t sl = sd >> 22;
         const uint32_t l = (sd >> 6) & 0xFFFFu;
-        const uint2 ht = (staged && sl == 0u) ? hown[l] : hist[smap[sl] * d.Ncol + l];
+        const uint2 ht = (staged && sl == 0u) ? hown[l] : hist[smap[k * kSlots + sl] * d.Ncol + l];
         const uint32_t m = ht.x >> dl;
         uint32_t dt;
         if (m) {
@@ -832,45 +845,52 @@ __device__ __forceinline__ void ltp_sparse_body(const NetDesc* __restrict__ nds,
     const uint32_t gw = wave_uniform(part * nw + (tid >> 6));
     const uint32_t gstride = nparts * nw;
     unsigned long long visits = 0;
-    uint32_t wd = gw, wbase = 0;
+    uint32_t g = gw, gk = 0, gbase = 0;
     unsigned long long m = 0;
     for (;;) {
         // up to 64 spiking neurons of this wavefront's words, one per lane
-        uint32_t cnt = 0, myl = 0;
+        uint32_t cnt = 0, myid = 0, myk = 0;
         while (cnt < 64u) {
             if (!m) {
-                if (wd >= d.W) break;
-                m = words[wd];
-                wbase = wd * 64u;
-                wd += gstride;
+                if (g >= nwords) break;
+                gk = g / d.W;
+                const uint32_t wd = g - gk * d.W;
+                m = ring[(size_t)ccol[gk] * d.W + wd];
+                gbase = ccol[gk] * d.Ncol + wd * 64u;
+                g += gstride;
                 continue;
             }
             const uint32_t b = (uint32_t)__ffsll((long long)m) - 1u;
             m &= m - 1ull;
-            if (lane == cnt) myl = wbase + b;
+            if (lane == cnt) {
+                myid = gbase + b;
+                myk = gk;
+            }
             ++cnt;
         }
         if (cnt == 0u) break;
-        uint32_t a = 0, e = 0;
+        uint64_t a = 0, e = 0;
         if (lane < cnt) {
-            a = (uint32_t)(rowptr[myl] - rb);
-            e = (uint32_t)(rowptr[myl + 1] - rb);
+            a = rowptr[myid];
+            e = rowptr[myid + 1];
             visits += e - a;
         }
-        const uint32_t nq = e > a ? ((e + 3u) >> 2) - (a >> 2) : 0u;
+        const uint32_t nq = e > a ? (uint32_t)(((e + 3u) >> 2) - (a >> 2)) : 0u;
         const uint32_t inc = wave_incl_scan(nq);
         const uint32_t exq = inc - nq;
         const uint32_t Q = (uint32_t)__shfl((int)inc, 63, 64);
         for (uint32_t base = 0; base < Q; base += 256u) {
-            uint32_t p[4], ra[4], re[4];
-            uint4 sd[4];
+            uint64_t p[4], ra[4], re[4];
+            uint32_t rk[4];
+            uint4 sdv[4];
             float4 pv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const uint32_t x = base + (uint32_t)u * 64u + lane;
                 const uint32_t r = wave_find_row(exq, x);
-                ra[u] = (uint32_t)__shfl((int)a, (int)r, 64);
-                re[u] = (uint32_t)__shfl((int)e, (int)r, 64);
+                ra[u] = (uint64_t)__shfl((long long)a, (int)r, 64);
+                re[u] = (uint64_t)__shfl((long long)e, (int)r, 64);
+                rk[u] = (uint32_t)__shfl((int)myk, (int)r, 64);
                 const uint32_t rx = (uint32_t)__shfl((int)exq, (int)r, 64);
                 p[u] = ((ra[u] >> 2) + (x - rx)) << 2;
                 if (x >= Q) re[u] = 0u;  // no entry of this quad is in a row
@@ -878,19 +898,19 @@ __device__ __forceinline__ void ltp_sparse_body(const NetDesc* __restrict__ nds,
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const bool any = re[u] != 0u;
-                sd[u] = any ? *(const uint4*)(rev_srcd + p[u]) : make_uint4(0u, 0u, 0u, 0u);
+                sdv[u] = any ? *(const uint4*)(rev_srcd + p[u]) : make_uint4(0u, 0u, 0u, 0u);
                 pv[u] = any ? *(const float4*)(P + p[u]) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const uint32_t q = p[u];
+                const uint64_t q = p[u];
                 const bool in0 = q >= ra[u] && q < re[u], in1 = q + 1u >= ra[u] && q + 1u < re[u];
                 const bool in2 = q + 2u >= ra[u] && q + 2u < re[u], in3 = q + 3u >= ra[u] && q + 3u < re[u];
                 float4 o = pv[u];
-                if (in0) o.x = ltp_one(sd[u].x, pv[u].x);
-                if (in1) o.y = ltp_one(sd[u].y, pv[u].y);
-                if (in2) o.z = ltp_one(sd[u].z, pv[u].z);
-                if (in3) o.w = ltp_one(sd[u].w, pv[u].w);
+                if (in0) o.x = ltp_one(rk[u], sdv[u].x, pv[u].x);
+                if (in1) o.y = ltp_one(rk[u], sdv[u].y, pv[u].y);
+                if (in2) o.z = ltp_one(rk[u], sdv[u].z, pv[u].z);
+                if (in3) o.w = ltp_one(rk[u], sdv[u].w, pv[u].w);
                 // a quad shared with another neuron's row keeps that row's entries
                 if (in0 && in1 && in2 && in3) {
                     *(float4*)(P + q) = o;
@@ -905,7 +925,8 @@ __device__ __forceinline__ void ltp_sparse_body(const NetDesc* __restrict__ nds,
         if (cnt < 64u) break;  // every word of this wavefront has been read
     }
     const unsigned long long v = block_sum64(visits, red64);
-    if (tid == 0 && v) atomicAdd(&nd.stats[ct & 63].ltp_visits, v);
+    // the stats slot of the first column (counters are only summed)
+    if (tid == 0 && v) atomicAdd(&nd.stats[ccol[0] & 63].ltp_visits, v);
 }
 
 // Sparse delivery.  One pass over the column's (delay, raster word) tasks
@@ -1166,8 +1187,9 @@ __device__ __forceinline__ void deliver_sparse_body(const NetDesc* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_ltp_sp(const NetDesc* __restrict__ nds,
                                                 const uint2* __restrict__ bmap, uint32_t nparts,
-                                                uint32_t allow_stage, uint32_t tstep) {
-    ltp_sparse_body(nds, bmap, nparts, allow_stage, tstep, blockIdx.x);
+                                                uint32_t allow_stage, uint32_t cpw, uint32_t nwg,
+                                                uint32_t n_entries, uint32_t tstep) {
+    ltp_sparse_body(nds, bmap, nparts, allow_stage, cpw, nwg, n_entries, tstep, blockIdx.x);
 }
 
 template <bool FIXED, typename TgtT>
@@ -1191,9 +1213,10 @@ __global__ __launch_bounds__(1024) void k_ltp_deliver(const NetDesc* __restrict_
                                                       uint32_t wslots,
                                                       unsigned long long* __restrict__ set_events,
                                                       uint32_t tstep, uint32_t n_ltp,
-                                                      uint32_t ltp_sparse) {
+                                                      uint32_t ltp_sparse, uint32_t cpw,
+                                                      uint32_t n_entries) {
     if (blockIdx.x < n_ltp && ltp_sparse)
-        ltp_sparse_body(nds, bmap, nparts, allow_stage, tstep, blockIdx.x);
+        ltp_sparse_body(nds, bmap, nparts, allow_stage, cpw, n_ltp, n_entries, tstep, blockIdx.x);
     else if (blockIdx.x < n_ltp)
         ltp_body<4>(nds, bmap, allow_stage, nparts, tstep, blockIdx.x);
     else
@@ -1210,7 +1233,7 @@ __global__ __launch_bounds__(256) void k_ltp_deliver_sp(const NetDesc* __restric
                                                         unsigned long long* __restrict__ set_events,
                                                         uint32_t tstep, uint32_t n_ltp) {
     if (blockIdx.x < n_ltp)
-        ltp_sparse_body(nds, bmap, nparts, allow_stage, tstep, blockIdx.x);
+        ltp_sparse_body(nds, bmap, nparts, allow_stage, 1u, n_ltp, n_ltp, tstep, blockIdx.x);
     else
         deliver_sparse_body<FIXED, TgtT>(nds, bmap, nparts, wslots, set_events, tstep,
                                          blockIdx.x - n_ltp);
@@ -1699,6 +1722,8 @@ struct FusedLtp {
     uint32_t allow_stage = 0;
     size_t lds = 0;
     uint32_t sparse = 0;   // LTP by the wavefront-level sparse body
+    uint32_t cpw = 1;      // sparse LTP: target columns per workgroup
+    uint32_t nwg = 0;      // sparse LTP workgroups when cpw > 1 (a multiple of 8)
 };
 
 template <typename TgtT>
@@ -1741,14 +1766,17 @@ hipError_t launch_deliver(LaunchSet& L, const Tuning& tune, hipStream_t stream, 
     const size_t lds = lds0 + (allow_age ? agew : 0);
     const uint32_t n_ltp = L.n_col * nparts;
     const uint32_t nblk = n_ltp * nsplit;
+    // LTP workgroups of the fused launch (fewer when one takes several columns)
+    const uint32_t n_ltpw = fl.cpw > 1u ? fl.nwg : n_ltp;
 #define DPSNN_DELIVER(FX, WN, UU)                                                              \
     do {                                                                                       \
         if (fl.on) {                                                                           \
             const size_t lf = std::max(lds, fl.lds);                                           \
             allow_lds(k_ltp_deliver<FX, WN, TgtT, UU>, lf);                                    \
-            hipLaunchKernelGGL((k_ltp_deliver<FX, WN, TgtT, UU>), dim3(n_ltp + nblk), dim3(BS),  \
+            hipLaunchKernelGGL((k_ltp_deliver<FX, WN, TgtT, UU>), dim3(n_ltpw + nblk), dim3(BS), \
                                lf, stream, L.descs, L.bmap_col, fl.allow_stage, allow_age,     \
-                               nparts, nsplit, wslots, L.ev_count, tstep, n_ltp, fl.sparse);   \
+                               nparts, nsplit, wslots, L.ev_count, tstep, n_ltpw, fl.sparse,   \
+                               fl.cpw, L.n_col);                                               \
         } else {                                                                               \
             allow_lds(k_deliver<FX, WN, TgtT, UU>, lds);                                       \
             hipLaunchKernelGGL((k_deliver<FX, WN, TgtT, UU>), dim3(nblk), dim3(BS), lds,       \
@@ -1813,7 +1841,7 @@ hipError_t launch_sparse(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream
     }
     tm.begin(0, stream);
     hipLaunchKernelGGL(k_ltp_sp, dim3(n), dim3(256), lds_l, stream, L.descs, L.bmap_col, nparts,
-                       allow_stage, tstep);
+                       allow_stage, 1u, n, n, tstep);
     tm.end(stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -1940,6 +1968,7 @@ Tuning effective_tuning(const LaunchSet& L, const Tuning& tune) {
     // the own column and two neighbour slots on larger ones (measured)
     if (t.own_slots == 0u) t.own_slots = (sparse && L.n_col >= 2048u) ? 3u : 1u;
     if (t.sparse_ltp == 2u) t.sparse_ltp = sparse ? 1u : 0u;
+    if (t.ltp_cols == 0u) t.ltp_cols = 1u;
     if (t.sparse_deliver == 2u) t.sparse_deliver = 0u;  // measured slower than the run path
     return t;
 }
@@ -1951,6 +1980,7 @@ bool same_shapes(const Tuning& a, const Tuning& b) {
            a.unroll == b.unroll && a.age == b.age && a.parts == b.parts && a.ltp_stage == b.ltp_stage &&
            a.fuse == b.fuse && a.split == b.split && a.own_slots == b.own_slots &&
            a.sparse_ltp == b.sparse_ltp && a.sparse_deliver == b.sparse_deliver &&
+           a.ltp_cols == b.ltp_cols &&
            a.max_lds == b.max_lds;
 }
 
@@ -1992,10 +2022,17 @@ hipError_t enqueue_step(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_
         fl.allow_stage = allow;
         fl.lds = lds;
         fl.sparse = ltp_sp ? 1u : 0u;
+        // several columns per sparse LTP workgroup: one network, unsplit columns
+        fl.cpw = (ltp_sp && L.K == 1 && nparts == 1u) ? std::max<uint32_t>(1u, tune.ltp_cols) : 1u;
+        if (fl.cpw > 1u) {
+            fl.nwg = ((L.n_col + fl.cpw - 1u) / fl.cpw + kXcds - 1u) / kXcds * kXcds;
+            fl.allow_stage = 0u;
+        }
         if (!fl.on && ltp_sp) {
+            const uint32_t nl = fl.cpw > 1u ? fl.nwg : L.n_col * nparts;
             tm.begin(0, stream);
-            hipLaunchKernelGGL(k_ltp_sp, dim3(L.n_col * nparts), dim3(256), lds, stream, L.descs,
-                               L.bmap_col, nparts, allow, tstep);
+            hipLaunchKernelGGL(k_ltp_sp, dim3(nl), dim3(256), lds, stream, L.descs,
+                               L.bmap_col, nparts, fl.allow_stage, fl.cpw, nl, L.n_col, tstep);
             tm.end(stream);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         } else if (!fl.on) {

@@ -213,6 +213,7 @@ TUNINGS = [
     ((12, 1),), ((12, 1), (10, 3)), ((12, 1), (10, 13)), ((12, 1), (5, 3)), ((12, 1), (7, 0)),
     ((12, 1), (10, 1), (5, 2), (7, 0)), ((11, 1),), ((11, 1), (7, 0)), ((11, 1), (6, 0), (5, 3)),
     ((11, 1), (2, 2), (4, 1), (10, 3)), ((11, 1), (0, 1024), (4, 1)),
+    ((11, 1), (13, 2)), ((11, 1), (13, 3), (7, 0)), ((11, 1), (13, 8), (0, 512)),
 ]
 
 
@@ -226,7 +227,8 @@ def test_dense_regime_column_parts(dp):
     assert (np.bincount(ref["tt"], minlength=T + 1)[110:] == 2500).sum() >= 20
     for tn in (((5, 13),), ((5, 200),), ((5, 9), (2, 2), (6, 0)), ((9, 2), (2, 1)),
                ((9, 5), (2, 1), (5, 3), (4, 1)), ((12, 1),), ((12, 1), (5, 13), (10, 2)),
-               ((12, 1), (7, 0), (10, 13)), ((11, 1),), ((11, 1), (2, 2), (4, 1), (5, 7))):
+               ((12, 1), (7, 0), (10, 13)), ((11, 1),), ((11, 1), (2, 2), (4, 1), (5, 7)),
+               ((11, 1), (13, 2))):
         g = gpu_run(dp, cfg, T, tuning=tn, conn=False)
         assert_bitexact(g, ref, conn=False)
         assert g["stats"]["events"] == ref["stats"]["events"]
@@ -251,6 +253,12 @@ def test_sparse_regime_shapes_invariance(dp):
     # first neighbour ring
     g5 = gpu_run(dp, cfg, T, tuning=((10, 5),), conn=False)
     assert_bitexact(g5, ref, conn=False)
+    # several target columns per sparse LTP workgroup (2048 columns: no padding;
+    # 3 and 7: the last workgroups take fewer columns)
+    for cpw in (2, 3, 7):
+        g = gpu_run(dp, cfg, T, tuning=((13, cpw),), conn=False)
+        assert_bitexact(g, ref, conn=False)
+        assert g["stats"]["ltp_visits"] == ref["stats"]["ltp_visits"]
 
 
 @pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
@@ -362,7 +370,8 @@ def test_tuning_and_step_arguments(dp):
     net = dp.Network(W.tiny(weight_update_period=40))
     try:
         for key, val in ((0, 300), (1, 100), (2, 4), (3, 3), (4, 3), (5, 1025), (6, 3),
-                         (8, 1025), (9, 0), (9, 14), (10, 14), (11, 3), (12, 3), (13, 1)):
+                         (8, 1025), (9, 0), (9, 14), (10, 14), (11, 3), (12, 3), (13, 9),
+                         (14, 1)):
             with pytest.raises(dp.DpsnnError) as e:
                 net.set_tuning(key, val)
             assert e.value.code == dp.E_INVAL, (key, val)
