@@ -141,7 +141,9 @@ int dpsnn_footprint_bytes(const dpsnn_config *cfg, uint64_t *bytes);
  * build has completed on the stream.  Size limits (DPSNN_E_INVAL beyond
  * them): fewer than 2^26 neurons, fewer than 2^36 synapses (2^32 with
  * DPSNN_SUM_ORDERED), and 13 x neurons_per_column x synapses_per_neuron
- * below 2^31. */
+ * below 2^31.  The build sorts each reverse row of up to 8192 entries by
+ * source, so the device layout is deterministic; results never depend on
+ * it. */
 int dpsnn_build_network(const dpsnn_config *cfg, const dpsnn_device *dev, dpsnn_net **out);
 
 /* Enqueue n_steps 1 ms steps (Sec. 2, loop items 2.1-2.7, plus the periodic
@@ -297,6 +299,11 @@ int dpsnn_set_timing(dpsnn_net *net, int enable);
  *          single networks with unsplit columns (key 5): a workgroup's time is
  *          set by its chain of dependent loads more than by its work, so
  *          fewer workgroups with more columns finish sooner; 0 = automatic
+ *   key 14: consolidation (Sec. 3, Table 2, "long term synaptic
+ *          plasticity"): 1 (default) one pass in forward order through the
+ *          network's forward-to-reverse map, kept when 13 x
+ *          neurons_per_column x synapses_per_neuron <= 2^28; 0 two passes
+ *          (reverse, then forward order), the form used without the map
  * (sparse / dense choice in parentheses) */
 int dpsnn_set_tuning(dpsnn_net *net, uint32_t key, uint32_t value);
 

@@ -42,6 +42,7 @@ struct Derived {
     uint32_t N, C, Ncol, Ne, M, Dmax, W, R, M_own;
     uint64_t S, S_exc;
     bool tgt16;
+    bool fwd_rev;  // consolidation's forward-to-reverse map is kept
 };
 
 bool finite_in(float x, float lo, float hi) { return std::isfinite(x) && x >= lo && x <= hi; }
@@ -104,6 +105,9 @@ int validate(const dpsnn_config* c, Derived* o) {
     o->S = S;
     o->S_exc = (uint64_t)C * Ne * o->M;
     o->tgt16 = (uint64_t)kSlots * Ncol <= 65536ull;
+    // the map packs a reverse offset inside the target column (below
+    // 13 * Ncol * M) into 28 bits next to the 4-bit slot
+    o->fwd_rev = o->S_exc > 0 && (uint64_t)kSlots * Ncol * o->M <= (1ull << 28);
     return DPSNN_OK;
 }
 
@@ -132,6 +136,7 @@ std::vector<size_t> array_bytes(const dpsnn_config* c, const Derived& d) {
         sizeof(uint64_t) * (N / 1024 + 2),                // scan_tmp
         sizeof(uint64_t) * ((size_t)d.C + 1),             // column starts of the reverse rows
     };
+    if (d.fwd_rev) b.push_back(sizeof(uint32_t) * S);     // fwd_rev
     if (c->sum_mode == DPSNN_SUM_ORDERED) {
         b.push_back(sizeof(uint32_t) * N);                // ev_cnt
         b.push_back(sizeof(uint32_t) * (N + 1));          // ev_start
@@ -471,6 +476,10 @@ int apply_tuning(Tuning& tn, uint32_t key, uint32_t value) {
             if (value > 8) return fail(DPSNN_E_INVAL, "columns per sparse LTP workgroup must be 0 (automatic) to 8");
             tn.ltp_cols = value;
             return DPSNN_OK;
+        case 14:
+            if (value > 1) return fail(DPSNN_E_INVAL, "consolidation must be 0 (two passes) or 1 (forward pass)");
+            tn.consolidate = value;
+            return DPSNN_OK;
         default:
             return fail(DPSNN_E_INVAL, "unknown tuning key");
     }
@@ -543,6 +552,7 @@ NetDesc Net::make_desc() const {
     nd.t0 = t;
     nd.colmap = colmap; nd.srcmap = srcmap; nd.seg_off = seg_off; nd.tgt = tgt;
     nd.w = w; nd.Dacc = Dacc; nd.rowptr = rowptr; nd.rev_srcd = rev_srcd; nd.rev_fwd = rev_fwd;
+    nd.fwd_rev = fwd_rev;
     nd.Pacc = Pacc; nd.v = v; nd.u = u; nd.acc = acc; nd.hist = hist;
     nd.t_last = t_last; nd.ring = ring; nd.tp = tp; nd.tm = tm; nd.tp_len = tp_len;
     nd.tm_len = tm_len; nd.stats = stats; nd.thal_whole = thal_whole; nd.thal_thr = thal_thr;
@@ -855,6 +865,7 @@ int dpsnn_build_network(const dpsnn_config* cfg, const dpsnn_device* dev, dpsnn_
     n->hist = (uint2*)p[k++]; n->t_last = (int32_t*)p[k++];
     n->ring = (uint64_t*)p[k++]; n->stats = (DevStats*)p[k++]; n->scan_tmp = (uint64_t*)p[k++];
     n->col_rev_dev = (uint64_t*)p[k++];
+    if (dv.fwd_rev) n->fwd_rev = (uint32_t*)p[k++];
     if (cfg->sum_mode == DPSNN_SUM_ORDERED) {
         n->ev_cnt = (uint32_t*)p[k++]; n->ev_start = (uint32_t*)p[k++];
         n->ev_key = (unsigned long long*)p[k++]; n->ev_w = (float*)p[k++];

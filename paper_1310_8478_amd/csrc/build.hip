@@ -8,7 +8,12 @@
 //      (in-degrees of the reverse index);
 //   2. k_col_scan / scan_u32: prefix sums give segment and reverse-row offsets;
 //   3. k_fill_rows: the same draws, ranked stably by delay with wave ballots,
-//      are written to their forward positions and reverse slots.
+//      are written to their forward positions and reverse slots;
+//   4. k_sort_rows / k_sort_long_rows: each reverse row sorted by (source
+//      slot, source neuron, delay, forward position), so a source column's
+//      entries in a row are one contiguous run;
+//   5. k_fwd_rev: for each excitatory forward position, its source slot and
+//      reverse entry (consolidation walks the forward order with it).
 #include "net.h"
 
 namespace dpsnn {
@@ -113,6 +118,117 @@ __global__ __launch_bounds__(256) void k_fill_rows(Dims d, const uint32_t* __res
             }
         }
         placed += (uint32_t)__popcll(same_delay(act, bb, lane + 1));
+    }
+}
+
+// Reverse rows sorted by the 64-bit key rev_srcd << 32 | rev_fwd (distinct
+// within a row).  The fill above claims row slots with atomics, so without
+// this the order inside a row depends on timing; sorted, the entries that
+// one source column sends to a row form one contiguous run (slot-major key).
+// No result depends on the order: rows longer than kSortLong stay as filled.
+constexpr uint32_t kSortShort = 1024;  // one wavefront per row, in LDS
+constexpr uint32_t kSortLong = 8192;   // one 1024-thread workgroup per row
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bitonic network over sk[0 .. P) (P a power of two), `lanes` threads from
+// `tid`, synchronised by `sync` after every stage.
+template <typename Sync>
+__device__ __forceinline__ void bitonic(unsigned long long* sk, uint32_t P, uint32_t tid,
+                                        uint32_t lanes, Sync sync) {
+    for (uint32_t k = 2u; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0u; j >>= 1) {
+            for (uint32_t x = tid; x < P; x += lanes) {
+                const uint32_t y = x ^ j;
+                if (y > x) {
+                    const unsigned long long a = sk[x], b = sk[y];
+                    if ((a > b) == ((x & k) == 0u)) {
+                        sk[x] = b;
+                        sk[y] = a;
+                    }
+                }
+            }
+            sync();
+        }
+    }
+}
+
+// Rows of 2 .. kSortShort entries: four rows per 256-thread workgroup, one
+// wavefront each.
+__global__ __launch_bounds__(256) void k_sort_rows(Dims d, const uint64_t* __restrict__ rowptr,
+                                                   uint32_t* __restrict__ rev_srcd,
+                                                   uint32_t* __restrict__ rev_fwd) {
+    __shared__ unsigned long long sk_all[4][kSortShort];
+    const uint32_t row = blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (row >= d.N) return;
+    const uint64_t x0 = rowptr[row];
+    const uint64_t len = rowptr[row + 1] - x0;
+    if (len < 2u || len > kSortShort) return;
+    const uint32_t n = (uint32_t)len;
+    unsigned long long* sk = sk_all[threadIdx.x >> 6];
+    const uint32_t lane = lane_id();
+    uint32_t P = 2u;
+    while (P < n) P <<= 1;
+    for (uint32_t x = lane; x < P; x += 64u)
+        sk[x] = x < n ? ((unsigned long long)rev_srcd[x0 + x] << 32 | rev_fwd[x0 + x]) : ~0ull;
+    wave_fence();
+    bitonic(sk, P, lane, 64u, wave_fence);
+    for (uint32_t x = lane; x < n; x += 64u) {
+        const unsigned long long k = sk[x];
+        rev_srcd[x0 + x] = (uint32_t)(k >> 32);
+        rev_fwd[x0 + x] = (uint32_t)k;
+    }
+}
+
+// Rows of kSortShort + 1 .. kSortLong entries: a 1024-thread workgroup per
+// row, the workgroups striding over all rows (the length test is uniform
+// across a workgroup, so every thread reaches every barrier).
+__global__ __launch_bounds__(1024) void k_sort_long_rows(Dims d, const uint64_t* __restrict__ rowptr,
+                                                         uint32_t* __restrict__ rev_srcd,
+                                                         uint32_t* __restrict__ rev_fwd) {
+    __shared__ unsigned long long sk[kSortLong];
+    for (uint32_t row = blockIdx.x; row < d.N; row += gridDim.x) {
+        const uint64_t x0 = rowptr[row];
+        const uint64_t len = rowptr[row + 1] - x0;
+        if (len <= kSortShort || len > kSortLong) continue;
+        const uint32_t n = (uint32_t)len;
+        uint32_t P = 2u;
+        while (P < n) P <<= 1;
+        for (uint32_t x = threadIdx.x; x < P; x += blockDim.x)
+            sk[x] = x < n ? ((unsigned long long)rev_srcd[x0 + x] << 32 | rev_fwd[x0 + x]) : ~0ull;
+        __syncthreads();
+        bitonic(sk, P, threadIdx.x, blockDim.x, [] { __syncthreads(); });
+        for (uint32_t x = threadIdx.x; x < n; x += blockDim.x) {
+            const unsigned long long k = sk[x];
+            rev_srcd[x0 + x] = (uint32_t)(k >> 32);
+            rev_fwd[x0 + x] = (uint32_t)k;
+        }
+        __syncthreads();  // sk is reused by the next row
+    }
+}
+
+// fwd_rev[f] = slot << 28 | (x - rowptr[ct * Ncol]) for the reverse entry x
+// (target column ct) of excitatory forward position f; positions of
+// inhibitory synapses keep 0xFFFFFFFF (slot 15) from the fill before.
+// Workgroups (target column, stripe); stripes walk the column's rows.
+__global__ __launch_bounds__(256) void k_fwd_rev(Dims d, const uint32_t* __restrict__ srcmap,
+                                                 const uint64_t* __restrict__ rowptr,
+                                                 const uint32_t* __restrict__ rev_srcd,
+                                                 const uint32_t* __restrict__ rev_fwd,
+                                                 uint32_t* __restrict__ fwd_rev) {
+    const uint32_t ct = blockIdx.x;
+    const uint64_t x0 = rowptr[(size_t)ct * d.Ncol];
+    const uint64_t x1 = rowptr[(size_t)(ct + 1) * d.Ncol];
+    const uint64_t colsz = (uint64_t)d.Ncol * d.M;
+    for (uint64_t x = x0 + (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; x < x1;
+         x += (uint64_t)gridDim.y * blockDim.x) {
+        const uint32_t slot = rev_srcd[x] >> 22;
+        const uint64_t f = (uint64_t)srcmap[ct * kSlots + slot] * colsz + rev_fwd[x];
+        fwd_rev[f] = slot << 28 | (uint32_t)(x - x0);
     }
 }
 
@@ -258,6 +374,19 @@ hipError_t launch_build(Net& n) {
         hipLaunchKernelGGL(k_fill_rows<uint32_t>, dim3(gb), dim3(256), 0, n.stream, d, n.colmap,
                            n.seg_off, (uint32_t*)n.tgt, n.w, n.rowptr, n.cursor, n.rev_srcd,
                            n.rev_fwd);
+    }
+    if (n.S_exc) {
+        hipLaunchKernelGGL(k_sort_rows, dim3((d.N + 3) / 4), dim3(256), 0, n.stream, d, n.rowptr,
+                           n.rev_srcd, n.rev_fwd);
+        // rows above kSortShort entries need in-degrees near M or above
+        if (d.M > kSortShort / 2)
+            hipLaunchKernelGGL(k_sort_long_rows, dim3(std::min<uint32_t>(d.N, 2048u)), dim3(1024), 0,
+                               n.stream, d, n.rowptr, n.rev_srcd, n.rev_fwd);
+    }
+    if (n.fwd_rev) {
+        if ((e = hipMemsetAsync(n.fwd_rev, 0xFF, 4 * (size_t)n.S, n.stream)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fwd_rev, dim3(d.C, 64), dim3(256), 0, n.stream, d, n.srcmap, n.rowptr,
+                           n.rev_srcd, n.rev_fwd, n.fwd_rev);
     }
     hipLaunchKernelGGL(k_init_state, dim3((d.N + 255) / 256), dim3(256), 0, n.stream, d, n.v, n.u,
                        n.hist, n.t_last);

@@ -55,6 +55,7 @@ struct NetDesc {
     const uint32_t* rev_srcd;        // [S_exc]
     const uint32_t* rev_fwd;         // [S_exc] forward position - c*Ncol*M of the source column c
     float* Pacc;                     // [S_exc]
+    const uint32_t* fwd_rev;         // [S] slot << 28 | reverse entry - target column start, or null
     float* v;
     float* u;
     void* acc;                       // long long or float [N]

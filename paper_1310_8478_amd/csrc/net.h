@@ -34,6 +34,7 @@ struct Tuning {
     uint32_t sparse_ltp = 2;      // wavefront-level LTP: 0 off, 1 on, 2 auto (on / off)
     uint32_t sparse_deliver = 2;  // wavefront-level delivery (and LTP): 0 off, 1 on, 2 auto (off)
     uint32_t ltp_cols = 0;        // target columns per sparse LTP workgroup, 1..8; 0 auto
+    uint32_t consolidate = 1;     // 1: one forward-order pass where fwd_rev exists; 0: two passes
     size_t max_lds = 65536;
 };
 
@@ -108,7 +109,10 @@ struct LaunchSet {
 //   reverse index of excitatory synapses, rows by global target id:
 //     rowptr[k] .. rowptr[k+1] (64-bit); rev_srcd = slot<<22 | local source<<6
 //     | delay; rev_fwd = forward position minus the source column's block
-//     start (32-bit); P = potentiation accumulator.
+//     start (32-bit); P = potentiation accumulator.  Rows up to 8192 entries
+//     are sorted by (rev_srcd, rev_fwd), so each source column's entries in
+//     a row are contiguous.
+//   fwd_rev: forward position -> source slot and reverse entry (consolidation).
 //   raster ring: R slots of C*W 64-bit words; stamp s lives in slot s % R.
 struct Net {
     dpsnn_config cfg;
@@ -136,6 +140,10 @@ struct Net {
     uint32_t* rev_srcd = nullptr; // [S_exc]
     uint32_t* rev_fwd = nullptr;  // [S_exc]
     float* Pacc = nullptr;        // [S_exc]
+    // [S] (when 13 * Ncol * M <= 2^28, else null): slot << 28 | reverse
+    // entry minus the first reverse position of the target column reached
+    // through slot; 0xFFFFFFFF at inhibitory positions
+    uint32_t* fwd_rev = nullptr;
     float* v = nullptr;
     float* u = nullptr;
     void* acc = nullptr;          // long long[N] (FIXED) or float[N]

@@ -1642,6 +1642,130 @@ __global__ __launch_bounds__(256) void k_wupdate(const NetDesc* __restrict__ nds
     }
 }
 
+// Consolidation in one pass over the forward order, for networks that keep
+// fwd_rev: for excitatory position f of column c with fwd_rev[f] = slot << 28
+// | o, the reverse entry is x = (first reverse position of the column
+// reached from c through slot) + o, and
+//   sd = P[x] - D[f]; w[f] <- clamp(w[f] + (bias + sd)); D[f] <- 0;
+//   P[x] <- decay * sd,
+// the same operations, in the same precision, as the two passes above.
+// Workgroup (column c, group q) takes the excitatory source neurons
+// [q*G, q*G + G) of c: their synapses of every delay, Dmax contiguous
+// ranges of the forward order, so w, D and fwd_rev stream (non-temporal
+// accesses: they are touched once and should not push P out of L2).  The
+// reverse rows are sorted by (slot, source, delay), so the P entries of a
+// run of source neurons are one short stretch of each target row's run for
+// that slot, and the few hundred source neurons in flight on an XCD (two
+// 1024-thread workgroups per CU) touch P lines that stay in its L2 until the
+// next neurons reuse them.  Work maps (`order`): with 1 and 2 all groups of
+// a column run on one XCD (the hardware hands workgroup b to XCD b mod 8);
+// for k = b / 8, step s = k / Q takes group k mod Q of
+//   1: column 8 s + b mod 8 (the eight XCDs on consecutive columns),
+//   2: column (x, y) = (8 (s / GY) + b mod 8, s mod GY): the XCDs walk the
+//      grid in strips of 8 columns, top to bottom, so the columns that share
+//      target columns run close together in time (grids with GX a multiple
+//      of 8);
+//   0: column b / Q, group b mod Q (fewer than 64 columns).
+constexpr uint32_t kConsUnroll = 4;      // forward positions in flight per thread
+constexpr uint32_t kConsSynapses = 2048; // synapses per workgroup (sets G)
+
+template <uint32_t U>
+__global__ __launch_bounds__(1024) void k_consolidate(const NetDesc* __restrict__ nds, uint32_t G,
+                                                      uint32_t Q, uint32_t order) {
+    __shared__ uint64_t base[16];  // first reverse position of the column in each slot
+    __shared__ uint64_t s0[32];    // first forward position of each delay's range
+    __shared__ uint32_t pre[33];   // prefix sums of the ranges' lengths
+    const NetDesc& nd = *nds;
+    const Dims d = nd.d;
+    uint32_t c, q;
+    if (order == 2u) {
+        const uint32_t k = blockIdx.x >> 3;
+        const uint32_t st = k / Q;
+        const uint32_t cx = (st / d.GY) * 8u + (blockIdx.x & 7u);
+        if (cx >= d.GX) return;
+        c = (st % d.GY) * d.GX + cx;
+        q = k % Q;
+    } else if (order == 1u) {
+        const uint32_t k = blockIdx.x >> 3;
+        c = (k / Q) * 8u + (blockIdx.x & 7u);
+        q = k % Q;
+    } else {
+        c = blockIdx.x / Q;
+        q = blockIdx.x % Q;
+    }
+    if (c >= d.C) return;
+    const uint32_t l0 = q * G;
+    const uint32_t l1 = min(l0 + G, d.Ne);
+    if (threadIdx.x < kSlots)
+        base[threadIdx.x] = nd.rowptr[(size_t)nd.colmap[c * kSlots + threadIdx.x] * d.Ncol];
+    if (threadIdx.x < 64u) {
+        // segment (delay k+1, neuron l) of column c starts at
+        // seg_off[c*segs + k*Ncol + l]; index k*Ncol + Ncol is the next
+        // delay's first segment (or the next column's, or the sentinel)
+        const uint32_t k = threadIdx.x;
+        uint32_t len = 0;
+        if (k < d.Dmax) {
+            const uint64_t* so = nd.seg_off + (size_t)c * d.segs + (size_t)k * d.Ncol;
+            const uint64_t a = so[l0];
+            s0[k] = a;
+            len = (uint32_t)(so[l1] - a);
+        }
+        uint32_t inc = len;
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (k >= (uint32_t)o) inc += y;
+        }
+        if (k < 32u) pre[k + 1] = inc;
+        if (k == 0u) pre[0] = 0u;
+    }
+    __syncthreads();
+    const uint32_t* __restrict__ fwd_rev = nd.fwd_rev;
+    float* __restrict__ P = nd.Pacc;
+    float* __restrict__ Dacc = nd.Dacc;
+    float* __restrict__ w = (float*)nd.w;
+    const float bias = nd.wu_bias, wmax = nd.w_max, decay = nd.sd_decay;
+    const uint32_t total = pre[d.Dmax];
+    for (uint32_t i0 = threadIdx.x; i0 < total; i0 += U * blockDim.x) {
+        // U positions per thread: every load issued before the first store
+        uint64_t f[U], x[U];
+        float dv[U], wv[U], pv[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * blockDim.x;
+            f[u] = ~0ull;
+            if (i < total) {
+                // the last range k with pre[k] <= i (empty ranges are skipped)
+                uint32_t lo = 0, hi = d.Dmax;
+                while (hi - lo > 1u) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (pre[mid] <= i) lo = mid;
+                    else hi = mid;
+                }
+                f[u] = s0[lo] + (i - pre[lo]);
+                const uint32_t code = __builtin_nontemporal_load(&fwd_rev[f[u]]);
+                x[u] = base[code >> 28] + (code & 0x0FFFFFFFu);
+                dv[u] = __builtin_nontemporal_load(&Dacc[f[u]]);
+                wv[u] = __builtin_nontemporal_load(&w[f[u]]);
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            if (f[u] != ~0ull) pv[u] = P[x[u]];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            if (f[u] == ~0ull) continue;
+            const float sd = pv[u] - dv[u];
+            float nw = wv[u] + (bias + sd);
+            if (nw < 0.0f) nw = 0.0f;
+            if (nw > wmax) nw = wmax;
+            __builtin_nontemporal_store(nw, &w[f[u]]);
+            __builtin_nontemporal_store(0.0f, &Dacc[f[u]]);
+            P[x[u]] = decay * sd;
+        }
+    }
+}
+
 // State probes (Sec. 2, "Production of observables": the trace of the
 // membrane potential and other state variables of individual neurons): after
 // the neuron update of step t, v and u of each probed neuron into row
@@ -1980,7 +2104,7 @@ bool same_shapes(const Tuning& a, const Tuning& b) {
            a.unroll == b.unroll && a.age == b.age && a.parts == b.parts && a.ltp_stage == b.ltp_stage &&
            a.fuse == b.fuse && a.split == b.split && a.own_slots == b.own_slots &&
            a.sparse_ltp == b.sparse_ltp && a.sparse_deliver == b.sparse_deliver &&
-           a.ltp_cols == b.ltp_cols &&
+           a.ltp_cols == b.ltp_cols && a.consolidate == b.consolidate &&
            a.max_lds == b.max_lds;
 }
 
@@ -2067,9 +2191,20 @@ hipError_t enqueue_step(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_
         if (!wu[k]) continue;
         const Net& n = *members[k];
         tm.begin(3, stream);
-        hipLaunchKernelGGL(k_wupdate, dim3(L.n_wu[k]), dim3(256), 0, stream, L.descs + k, L.bmap_wu[k]);
-        const uint64_t nfwd = ((uint64_t)n.S + 256ull * kWupdateItems - 1) / (256ull * kWupdateItems);
-        hipLaunchKernelGGL(k_wupdate_fwd, dim3((uint32_t)nfwd), dim3(256), 0, stream, L.descs + k);
+        if (n.fwd_rev && tune.consolidate) {
+            const uint32_t G = std::max<uint32_t>(1u, (kConsSynapses + n.d.M - 1u) / n.d.M);
+            const uint32_t Q = (n.d.Ne + G - 1u) / G;
+            const uint32_t order = n.d.C < 64u ? 0u : (n.d.GX % 8u == 0u ? 2u : 1u);
+            const uint64_t nwg = order == 2u ? 8ull * Q * (n.d.GX / 8u) * n.d.GY
+                                 : order == 1u ? 8ull * Q * ((n.d.C + 7u) / 8u)
+                                               : (uint64_t)Q * n.d.C;
+            hipLaunchKernelGGL(k_consolidate<kConsUnroll>, dim3((uint32_t)nwg), dim3(1024), 0, stream,
+                               L.descs + k, G, Q, order);
+        } else {
+            hipLaunchKernelGGL(k_wupdate, dim3(L.n_wu[k]), dim3(256), 0, stream, L.descs + k, L.bmap_wu[k]);
+            const uint64_t nfwd = ((uint64_t)n.S + 256ull * kWupdateItems - 1) / (256ull * kWupdateItems);
+            hipLaunchKernelGGL(k_wupdate_fwd, dim3((uint32_t)nfwd), dim3(256), 0, stream, L.descs + k);
+        }
         tm.end(stream);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

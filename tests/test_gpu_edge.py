@@ -114,8 +114,9 @@ def test_edge_configuration_sparse_path_bitexact(dp, orc, name):
     assert_bitexact(g, o)
     assert g["stats"]["events"] == o["counters"]["events"]
     assert g["stats"]["ltp_visits"] == o["counters"]["ltp_visits"]
-    # the sparse LTP beside the run-based delivery, with the partial-window ages
-    g = gpu_run(dp, cfg, T, tuning=((11, 1), (2, 2), (4, 1)))
+    # the sparse LTP beside the run-based delivery, with the partial-window
+    # ages, and consolidation as the two reverse-order passes
+    g = gpu_run(dp, cfg, T, tuning=((11, 1), (2, 2), (4, 1), (14, 0)))
     assert_bitexact(g, o)
     assert g["stats"]["events"] == o["counters"]["events"]
     assert g["stats"]["ltp_visits"] == o["counters"]["ltp_visits"]

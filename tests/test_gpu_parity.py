@@ -214,6 +214,8 @@ TUNINGS = [
     ((12, 1), (10, 1), (5, 2), (7, 0)), ((11, 1),), ((11, 1), (7, 0)), ((11, 1), (6, 0), (5, 3)),
     ((11, 1), (2, 2), (4, 1), (10, 3)), ((11, 1), (0, 1024), (4, 1)),
     ((11, 1), (13, 2)), ((11, 1), (13, 3), (7, 0)), ((11, 1), (13, 8), (0, 512)),
+    # consolidation as two passes in reverse order instead of the forward pass
+    ((14, 0),), ((14, 0), (7, 0), (12, 1)),
 ]
 
 
@@ -228,7 +230,7 @@ def test_dense_regime_column_parts(dp):
     for tn in (((5, 13),), ((5, 200),), ((5, 9), (2, 2), (6, 0)), ((9, 2), (2, 1)),
                ((9, 5), (2, 1), (5, 3), (4, 1)), ((12, 1),), ((12, 1), (5, 13), (10, 2)),
                ((12, 1), (7, 0), (10, 13)), ((11, 1),), ((11, 1), (2, 2), (4, 1), (5, 7)),
-               ((11, 1), (13, 2))):
+               ((11, 1), (13, 2)), ((14, 0),), ((14, 0), (5, 13))):
         g = gpu_run(dp, cfg, T, tuning=tn, conn=False)
         assert_bitexact(g, ref, conn=False)
         assert g["stats"]["events"] == ref["stats"]["events"]
@@ -371,7 +373,7 @@ def test_tuning_and_step_arguments(dp):
     try:
         for key, val in ((0, 300), (1, 100), (2, 4), (3, 3), (4, 3), (5, 1025), (6, 3),
                          (8, 1025), (9, 0), (9, 14), (10, 14), (11, 3), (12, 3), (13, 9),
-                         (14, 1)):
+                         (14, 2), (15, 1)):
             with pytest.raises(dp.DpsnnError) as e:
                 net.set_tuning(key, val)
             assert e.value.code == dp.E_INVAL, (key, val)
@@ -429,14 +431,16 @@ def test_mid_full_size_window_bitexact(dp, orc):
 
 
 @pytest.mark.parametrize("mode", [W.SUM_FIXED, W.SUM_ORDERED])
-def test_many_columns_bitexact(dp, orc, mode):
-    # 77 columns (eighths of 9 and 10): a single network of 64 columns or more
-    # is dispatched in an XCD-aware column order
-    cfg = W.make_config(grid_x=11, grid_y=7, neurons_per_column=60, synapses_per_neuron=30,
+@pytest.mark.parametrize("grid", [(11, 7), (16, 4)])
+def test_many_columns_bitexact(dp, orc, mode, grid):
+    # a single network of 64 columns or more is dispatched in an XCD-aware
+    # column order; 11x7 (77 columns, eighths of 9 and 10) takes the
+    # consolidation's interleaved work map, 16x4 its strip map
+    cfg = W.make_config(grid_x=grid[0], grid_y=grid[1], neurons_per_column=60, synapses_per_neuron=30,
                         thalamic_rate=3.0, w_exc_init=9.0, weight_update_period=70,
                         sum_mode=mode, seed=7707)
     T = 160
-    _say(f"11x7 grid, mode {mode}")
+    _say(f"{grid[0]}x{grid[1]} grid, mode {mode}")
     g = gpu_run(dp, cfg, T)
     o = oracle_run(orc, cfg, T)
     assert_bitexact(g, o)
