@@ -150,7 +150,7 @@ def _kernel_table(d, bytes_k):
     return kern
 
 
-def bench_batched(args, mode):
+def run_batched(n_nets, warmup, steps, mode, mode_name):
     """Many independent networks of uneven size advanced together (one launch
     per kernel for all of them), against the same networks stepped one at a
     time.  Both sets start from t = 0 and are timed over the same steps."""
@@ -158,7 +158,7 @@ def bench_batched(args, mode):
     from paper_1310_8478_amd import dpsnn as dp
     from paper_1310_8478_amd import workloads as W
 
-    cfgs = [dict(c, sum_mode=mode) for c in W.batched_mix(args.nets)]
+    cfgs = [dict(c, sum_mode=mode) for c in W.batched_mix(n_nets)]
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     nets = [dp.Network(c, device=0) for c in cfgs]
@@ -169,23 +169,23 @@ def bench_batched(args, mode):
           file=sys.stderr, flush=True)
     batch = dp.Batch(nets)
     tune_steps = 0
-    if args.warmup >= 36:
+    if warmup >= 36:
         batch.autotune(steps_per_trial=3)       # 2 rounds x 6 shapes x 3 steps
         tune_steps = 36
-    if args.warmup > tune_steps:
-        batch.step(args.warmup - tune_steps)
+    if warmup > tune_steps:
+        batch.step(warmup - tune_steps)
     batch.set_timing(True)
     s0 = batch.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
-    while done < args.steps:
-        k = min(100, args.steps - done)
+    while done < steps:
+        k = min(100, steps - done)
         batch.step(k)
         done += k
-        if done % 500 == 0 or done == args.steps:
+        if done % 500 == 0 or done == steps:
             torch.cuda.synchronize()
-            print(f"[bench] batched {done}/{args.steps} steps", file=sys.stderr, flush=True)
+            print(f"[bench] batched {done}/{steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s1 = batch.stats()
@@ -197,16 +197,16 @@ def bench_batched(args, mode):
     # the same networks, stepped one network at a time
     seq = [dp.Network(c, device=0) for c in cfgs]
     for n in seq:
-        n.step(args.warmup)
+        n.step(warmup)
     torch.cuda.synchronize()
     e0 = sum(n.stats()["events"] for n in seq)
     t0 = time.perf_counter()
-    for step in range(args.steps):
+    for step in range(steps):
         for n in seq:
             n.step(1)
         if (step + 1) % 500 == 0:
             torch.cuda.synchronize()
-            print(f"[bench] one-by-one {step + 1}/{args.steps} steps", file=sys.stderr, flush=True)
+            print(f"[bench] one-by-one {step + 1}/{steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall_seq = time.perf_counter() - t0
     e1 = sum(n.stats()["events"] for n in seq)
@@ -230,18 +230,14 @@ def bench_batched(args, mode):
             "frac": round(ach / HBM_PEAK_GBS, 4) if ach else None, "traffic": None,
             "kernel": f"k_{dom}", "avg_launch_us": kern[dom]["avg_us"],
             "algo_bytes_per_launch": kern[dom]["algo_bytes_per_launch"]}
-    cpu = None
-    if not args.no_cpu:
-        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(cfgs[0], args.cpu_seconds)
     sides = sorted(c["grid_x"] for c in cfgs)
-    rate_hz = d["spikes"] / N / (args.steps / 1000.0)
-    out = {
+    rate_hz = d["spikes"] / N / (steps / 1000.0)
+    return {
         "metric": "synaptic events/s",
         "value": d["events"] / wall,
         "unit": "events/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1000.0 * wall / args.steps,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": 1000.0 * wall / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if mode != W.SUM_FIXED else "f32+i64acc",
         "data": "synthetic (seeded Philox networks and thalamic input, as in the paper)",
@@ -249,8 +245,8 @@ def bench_batched(args, mode):
             "workload": (f"batched: {len(cfgs)} independent networks, square grids of side "
                          f"{sides[0]}..{sides[-1]} x 1250 neurons, M 100-400, thalamic 0.5-2/column/ms, "
                          f"seeds 2000+b, one launch per kernel for all networks, autotuned shapes"),
-            "neurons": N, "synapses": S, "sum_mode": args.mode,
-            "timed_steps": f"{args.warmup}..{args.warmup + args.steps - 1}",
+            "neurons": N, "synapses": S, "sum_mode": mode_name,
+            "timed_steps": f"{warmup}..{warmup + steps - 1}",
         },
         "one_by_one_events_per_s": (e1 - e0) / wall_seq,
         "batch_speedup": (d["events"] / wall) / ((e1 - e0) / wall_seq) if e1 > e0 else None,
@@ -258,18 +254,27 @@ def bench_batched(args, mode):
         "build_s": build_s,
         "kernels": kern,
         "roofline": roof,
-        "cpu_baseline": cpu,
+        "first_config": cfgs[0],
     }
+
+
+def bench_batched(args, mode):
+    out = run_batched(args.nets, args.warmup, args.steps, mode, args.mode)
+    cfg0 = out.pop("first_config")
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg0, args.cpu_seconds)
+    out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
-def bench_serving(args, mode):
-    """Continuous-batching serving: a Poisson stream of jobs (uneven networks,
-    100-2000 steps each) submitted at their arrival times to a job server that
-    admits them by device footprint and steps every admitted job together.
-    Latency = result readable (last step completed) - submission, build
-    included.  Throughput = events of all jobs / (last completion - first
-    submission)."""
+def run_serving(reqs, budget_gb, quantum, warmup_jobs, mode, mode_name, jobs_out="", label=""):
+    """Continuous-batching serving: a Poisson stream of jobs (uneven networks)
+    submitted at their arrival times to a job server that admits them by
+    device footprint and steps every admitted job together.  Latency = result
+    readable (last step completed) - submission, build included.  Throughput
+    = events of all jobs / (last completion - first submission)."""
     import threading
 
     import numpy as np
@@ -278,13 +283,12 @@ def bench_serving(args, mode):
     from paper_1310_8478_amd import workloads as W
 
     torch.cuda.set_device(0)
-    reqs = W.serving_stream(args.requests, lam=args.rate)
     for r in reqs:
         r["config"] = dict(r["config"], sum_mode=mode)
-    srv = dp.Server(device=0, budget_bytes=int(args.budget_gb * 1e9), max_quantum=args.quantum)
+    srv = dp.Server(device=0, budget_bytes=int(budget_gb * 1e9), max_quantum=quantum)
     # warm-up jobs (not timed): load the kernels and fill the allocator's cache
     warm = [srv.submit(W.make_config(grid_x=4, grid_y=4, synapses_per_neuron=300, sum_mode=mode,
-                                     seed=9000 + k), 50) for k in range(max(0, args.warmup_jobs))]
+                                     seed=9000 + k), 50) for k in range(max(0, warmup_jobs))]
     for j in warm:
         srv.wait(j)
         srv.release(j)
@@ -332,8 +336,8 @@ def bench_serving(args, mode):
     if errors:
         raise RuntimeError("; ".join(errors[:5]))
 
-    if args.jobs_out:
-        with open(args.jobs_out, "w") as f:
+    if jobs_out:
+        with open(jobs_out, "w") as f:
             json.dump([dict(d, grid=reqs[d["id"] - len(warm) - 1]["config"]["grid_x"],
                             M=reqs[d["id"] - len(warm) - 1]["config"]["synapses_per_neuron"])
                        for d in done], f)
@@ -347,6 +351,9 @@ def bench_serving(args, mode):
     job_steps = sum(r["steps"] for r in reqs)
     syn = [r["config"]["grid_x"] * r["config"]["grid_y"] * r["config"]["neurons_per_column"]
            * r["config"]["synapses_per_neuron"] for r in reqs]
+    sides = [r["config"]["grid_x"] for r in reqs]
+    durs = [r["steps"] for r in reqs]
+    rate = len(reqs) / reqs[-1]["arrival"] if reqs[-1]["arrival"] > 0 else None
     out = {
         "metric": "synaptic events/s",
         "value": events / span,
@@ -357,11 +364,13 @@ def bench_serving(args, mode):
         "dtype": "f32" if mode != W.SUM_FIXED else "f32+i64acc",
         "data": "synthetic (seeded Philox networks and thalamic input, as in the paper)",
         "config": {
-            "workload": (f"serving: {len(reqs)} jobs, Poisson arrivals at {args.rate}/s, square grids "
-                         f"of side 4..32 x 1250 neurons, M 100-625, 100-2000 steps, seeds 3000+k, "
-                         f"admission by footprint within {args.budget_gb:g} GB"),
-            "sum_mode": args.mode, "max_quantum": args.quantum,
+            "workload": (f"serving{label}: {len(reqs)} jobs, Poisson arrivals (offered "
+                         f"{rate:.2f}/s), square grids of side {min(sides)}..{max(sides)} x 1250 "
+                         f"neurons, M 100-625, {min(durs)}-{max(durs)} steps, seeds 3000+k, "
+                         f"admission by footprint within {budget_gb:g} GB"),
+            "sum_mode": mode_name, "max_quantum": quantum,
             "synapses_per_job_mean": float(np.mean(syn)),
+            "events_per_job_mean": events / max(1, len(done)),
         },
         "serve_p50_s": float(np.percentile(lat, 50)),
         "serve_p99_s": float(np.percentile(lat, 99)),
@@ -378,6 +387,14 @@ def bench_serving(args, mode):
         "roofline": None,
         "cpu_baseline": None,
     }
+    return out
+
+
+def bench_serving(args, mode):
+    from paper_1310_8478_amd import workloads as W
+    reqs = W.serving_stream(args.requests, lam=args.rate)
+    out = run_serving(reqs, args.budget_gb, args.quantum, args.warmup_jobs, mode, args.mode,
+                      jobs_out=args.jobs_out)
     print(json.dumps(out))
 
 
@@ -477,6 +494,14 @@ def bench_paper(args, mode):
         "roofline": None,
         "cpu_baseline": None,
     }
+    return out
+
+
+def bench_serving(args, mode):
+    from paper_1310_8478_amd import workloads as W
+    reqs = W.serving_stream(args.requests, lam=args.rate)
+    out = run_serving(reqs, args.budget_gb, args.quantum, args.warmup_jobs, mode, args.mode,
+                      jobs_out=args.jobs_out)
     print(json.dumps(out))
 
 
@@ -590,6 +615,10 @@ def main():
     ap.add_argument("--no-startup", action="store_true", help="large: skip the start-up window")
     ap.add_argument("--no-paper-rate", action="store_true",
                     help="large: skip the window on the paper's 128x128 grid at its own rates")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="large: skip the window on the batched mix of 32 networks")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="large: skip the job-server window at a load the device carries")
     ap.add_argument("--paper-rate-evolve", type=int, default=8000)
     ap.add_argument("--paper-rate-steps", type=int, default=200)
     ap.add_argument("--nets", type=int, default=32, help="networks in the batched workload")
@@ -702,6 +731,26 @@ def main():
                                 "evolved_steps": args.paper_rate_evolve}
         pnet.close()
 
+    batched = None
+    if large and not args.no_batched:
+        # the batched mix: 32 uneven networks in one launch set (41 warm-up
+        # steps: 36 of autotuning), against the same networks one at a time
+        b = run_batched(32, 41, 200, mode, args.mode)
+        b.pop("first_config")
+        batched = {k: b[k] for k in ("value", "unit", "ms_per_step", "one_by_one_events_per_s",
+                                     "batch_speedup", "rate_hz", "build_s", "roofline", "config")}
+    serving = None
+    if large and not args.no_serving:
+        # the job server at a load it carries: 60 jobs (sides 4..16, 100..500
+        # steps) arriving at 4/s, so latency is service time, not queueing
+        reqs = W.serving_stream(60, lam=4.0, max_side=16, max_steps=500)
+        sv = run_serving(reqs, args.budget_gb, args.quantum, 2, mode, args.mode, label=" (light load)")
+        serving = {k: sv[k] for k in ("value", "unit", "serve_p50_s", "serve_p99_s", "serve_max_s",
+                                      "queue_wait_mean_s", "build_mean_s", "jobs_per_s", "span_s",
+                                      "arrivals_span_s", "peak_running", "config")}
+        serving["offered_events_per_s"] = (sv["config"]["events_per_job_mean"] * len(reqs)
+                                           / reqs[-1]["arrival"])
+
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
@@ -744,6 +793,8 @@ def main():
         "roofline": head["roofline"],
         "startup": startup,
         "paper_rate": paper_rate,
+        "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

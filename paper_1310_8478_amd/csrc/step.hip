@@ -1341,40 +1341,70 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One target's n (kSelectFold < n <= kLdsSort) events sorted by key by all 64
-// lanes of a wavefront in the wavefront's LDS arrays sk / sw: loaded padded
-// to a power of two with keys above every real key, then a bitonic network.
-// Called with the whole wavefront active; the sorted events stay in LDS.
-__device__ __forceinline__ void wave_sort_events(const unsigned long long* __restrict__ key,
-                                                 const float* __restrict__ wt, uint32_t n,
-                                                 unsigned long long* __restrict__ sk,
-                                                 float* __restrict__ sw) {
-    const uint32_t lane = lane_id();
+// Bitonic sort of one target's events by the 64 lanes of a wavefront, in
+// two helpers that a host test also runs (lane by lane, which is the same
+// computation: the pairs of one stage are disjoint):
+// wave_sort_load: the n events into sk / sw, padded to P (a power of two,
+// at least 64) with keys above every real key; bitonic_stage: the
+// compare-exchange stage (k, j) for the elements lane, lane + 64, ... .
+__device__ __forceinline__ uint32_t wave_sort_load(const unsigned long long* __restrict__ key,
+                                                   const float* __restrict__ wt, uint32_t n,
+                                                   unsigned long long* __restrict__ sk,
+                                                   float* __restrict__ sw, uint32_t lane) {
     uint32_t P = 64u;
     while (P < n) P <<= 1;
     for (uint32_t x = lane; x < P; x += 64u) {
         sk[x] = x < n ? key[x] : ~0ull;
         sw[x] = x < n ? wt[x] : 0.0f;
     }
+    return P;
+}
+
+__device__ __forceinline__ void bitonic_stage(unsigned long long* __restrict__ sk,
+                                              float* __restrict__ sw, uint32_t P, uint32_t k,
+                                              uint32_t j, uint32_t lane) {
+    for (uint32_t x = lane; x < P; x += 64u) {
+        const uint32_t y = x ^ j;
+        if (y > x) {
+            const unsigned long long a = sk[x], b = sk[y];
+            if ((a > b) == ((x & k) == 0u)) {
+                sk[x] = b;
+                sk[y] = a;
+                const float wa = sw[x];
+                sw[x] = sw[y];
+                sw[y] = wa;
+            }
+        }
+    }
+}
+
+// One target's n (kSelectFold < n <= kLdsSort) events sorted by key by all 64
+// lanes of a wavefront in the wavefront's LDS arrays sk / sw.  Called with
+// the whole wavefront active; the sorted events stay in LDS.
+__device__ __forceinline__ void wave_sort_events(const unsigned long long* __restrict__ key,
+                                                 const float* __restrict__ wt, uint32_t n,
+                                                 unsigned long long* __restrict__ sk,
+                                                 float* __restrict__ sw) {
+    const uint32_t lane = lane_id();
+    const uint32_t P = wave_sort_load(key, wt, n, sk, sw, lane);
     wave_sync();
     for (uint32_t k = 2u; k <= P; k <<= 1) {
         for (uint32_t j = k >> 1; j > 0u; j >>= 1) {
-            for (uint32_t x = lane; x < P; x += 64u) {
-                const uint32_t y = x ^ j;
-                if (y > x) {
-                    const unsigned long long a = sk[x], b = sk[y];
-                    if ((a > b) == ((x & k) == 0u)) {
-                        sk[x] = b;
-                        sk[y] = a;
-                        const float wa = sw[x];
-                        sw[x] = sw[y];
-                        sw[y] = wa;
-                    }
-                }
-            }
+            bitonic_stage(sk, sw, P, k, j, lane);
             wave_sync();
         }
     }
+}
+
+// The fp32 fold of a neuron's external input of the step, onto a: its
+// thalamic hits, then its stimulus entries in list order.
+__device__ __forceinline__ float fold_external(float a, uint32_t hits, float thal_mv, uint32_t sb,
+                                               uint32_t se, const uint32_t* __restrict__ stim_id,
+                                               const float* __restrict__ stim_mv, uint32_t k) {
+    for (uint32_t h = 0; h < hits; ++h) a = a + thal_mv;
+    for (uint32_t e = sb; e < se; ++e)
+        if (stim_id[e] == k) a = a + stim_mv[e];
+    return a;
 }
 
 // One target's n events of a step, sorted in place by key (weights move
@@ -1496,12 +1526,7 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
         const uint32_t ne = valid ? ev_cnt[kk] : 0u;
         const uint32_t b0 = valid ? ev_start[kk] : 0u;
         const bool mine = valid && ne > kSelectFold && ne <= kLdsSort;
-        if (mine) {
-            const uint32_t hits = thc[wv][lane];
-            for (uint32_t h = 0; h < hits; ++h) lds_fold = lds_fold + thal_mv;
-            for (uint32_t e = sb; e < se; ++e)
-                if (stim_id[e] == kk) lds_fold = lds_fold + stim_mv[e];
-        }
+        if (mine) lds_fold = fold_external(0.0f, thc[wv][lane], thal_mv, sb, se, stim_id, stim_mv, kk);
         unsigned long long big = __ballot(mine);
         while (big) {
             const uint32_t src = (uint32_t)__ffsll((long long)big) - 1u;
@@ -1522,14 +1547,12 @@ __global__ __launch_bounds__(256) void k_neuron(const NetDesc* __restrict__ nds,
         float a32 = 0.0f;
         if (MODE == DPSNN_SUM_FIXED) a64 = ((long long*)acc_v)[k];
         if (MODE == DPSNN_SUM_ATOMIC) a32 = ((float*)acc_v)[k];
-        const long long q_thal = to_fixed(thal_mv);
-        if (MODE == DPSNN_SUM_FIXED) a64 += (long long)hits * q_thal;
-        else for (uint32_t h = 0; h < hits; ++h) a32 = a32 + thal_mv;
-        for (uint32_t e = sb; e < se; ++e) {
-            if (stim_id[e] == k) {
-                if (MODE == DPSNN_SUM_FIXED) a64 += to_fixed(stim_mv[e]);
-                else a32 = a32 + stim_mv[e];
-            }
+        if (MODE == DPSNN_SUM_FIXED) {
+            a64 += (long long)hits * to_fixed(thal_mv);
+            for (uint32_t e = sb; e < se; ++e)
+                if (stim_id[e] == k) a64 += to_fixed(stim_mv[e]);
+        } else {
+            a32 = fold_external(a32, hits, thal_mv, sb, se, stim_id, stim_mv, k);
         }
         if (MODE == DPSNN_SUM_ORDERED) {
             // canonical-order fold of this step's deliveries (keys are

@@ -145,17 +145,19 @@ def batched_mix(n_nets: int = 32, seed: int = 8478) -> list[dict]:
     return out
 
 
-def serving_stream(n_req: int = 400, lam: float = 20.0, seed: int = 8479):
+def serving_stream(n_req: int = 400, lam: float = 20.0, seed: int = 8479, max_side: int = 32,
+                   max_steps: int = 2000):
     """Poisson request stream: inter-arrival Exp(lam) seconds; square grid side
-    U{4..32}; M ~ U{100..625}; duration ~ U{100..2000} steps; seed 3000 + k."""
+    U{4..max_side}; M ~ U{100..625}; duration ~ U{100..max_steps} steps;
+    seed 3000 + k."""
     rng = np.random.default_rng(seed)
     t = 0.0
     reqs = []
     for k in range(n_req):
         t += float(rng.exponential(1.0 / lam))
-        side = int(rng.integers(4, 33))
+        side = int(rng.integers(4, max_side + 1))
         M = int(rng.integers(100, 626))
-        steps = int(rng.integers(100, 2001))
+        steps = int(rng.integers(100, max_steps + 1))
         reqs.append(dict(arrival=t, steps=steps,
                          config=make_config(grid_x=side, grid_y=side,
                                             synapses_per_neuron=M, seed=3000 + k)))
