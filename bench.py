@@ -398,6 +398,52 @@ def bench_serving(args, mode):
     print(json.dumps(out))
 
 
+def bench_consolidation(args, mode):
+    """Consolidation alone (Sec. 3, Table 2, "long term synaptic plasticity"):
+    Table 1's 128x128 grid and the large workload, consolidating every 40
+    steps for 121 steps (three passes), in the one-pass forward form (tuning
+    key 14 = 1) and the two-pass form (0), timed by the per-kernel timers."""
+    import torch
+    from paper_1310_8478_amd import dpsnn as dp
+    from paper_1310_8478_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    rows = {}
+    for name, make in (("paper128", W.paper128), ("large", W.large)):
+        cfg = make(weight_update_period=40, sum_mode=mode)
+        exc_syn = cfg["grid_x"] * cfg["grid_y"] * round(cfg["exc_fraction"] * cfg["neurons_per_column"]) \
+            * cfg["synapses_per_neuron"]
+        for key in (1, 0):
+            net = dp.Network(cfg, device=0)
+            try:
+                net.set_tuning(14, key)
+                net.set_timing(True)
+                net.step(121)
+                net.sync()
+                st = net.stats()
+            finally:
+                net.close()
+            ms = st["ms_wupdate"] / max(1, st["n_wupdate"])
+            gbs = exc_syn * BYTES_CONSOLIDATION / (ms * 1e-3) / 1e9
+            rows[f"{name}_{'forward' if key else 'two_pass'}"] = {
+                "ms_per_pass": ms, "passes": st["n_wupdate"], "algo_bytes": exc_syn * BYTES_CONSOLIDATION,
+                "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
+            print(f"[bench] consolidation {name}, key 14 = {key}: {ms:.2f} ms per pass",
+                  file=sys.stderr, flush=True)
+    head = rows["paper128_forward"]
+    print(json.dumps({
+        "metric": "consolidation time per pass", "value": head["ms_per_pass"], "unit": "ms",
+        "n_gpus": 1, "steps": 121, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if mode != W.SUM_FIXED else "f32+i64acc",
+        "data": "synthetic (seeded Philox networks and thalamic input, as in the paper)",
+        "config": {"workload": "consolidation every 40 steps, 121 steps: Table 1 128x128 grid and the "
+                               "large workload, forward and two-pass forms"},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["frac"], "traffic": None, "kernel": "k_consolidate"},
+        "runs": rows, "cpu_baseline": None}))
+
+
 def bench_paper(args, mode):
     """The paper's own experiment shapes on one GPU: the Table 1 scaling grids
     (1000-neuron columns, M = 200, 76/12/8/4 % projection) and the Table 3
@@ -608,7 +654,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="large",
-                    choices=["tiny", "mid", "large", "paper128", "batched", "serving", "paper"])
+                    choices=["tiny", "mid", "large", "paper128", "batched", "serving", "paper",
+                             "consolidation"])
     ap.add_argument("--evolve", type=int, default=None,
                     help="steps the network evolves (untimed) before the warm-up; default 150 "
                          "for large (all-firing from about step 100), 0 otherwise")
@@ -665,6 +712,8 @@ def main():
         return bench_serving(args, mode)
     if args.workload == "paper":
         return bench_paper(args, mode)
+    if args.workload == "consolidation":
+        return bench_consolidation(args, mode)
     make, _ = W.WORKLOADS[args.workload]
     cfg = make(sum_mode=mode)
     large = args.workload == "large"
