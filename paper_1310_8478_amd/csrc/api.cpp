@@ -580,8 +580,9 @@ struct dpsnn_batch {
 // A checkpoint holds the configuration and the dynamic state; the
 // connectivity is regenerated from the seed when it is loaded.  Layout: the
 // header, then the arrays of ckpt_parts in order, each padded to 16 bytes.
-// P is stored in the forward layout: the order of entries inside a reverse
-// row depends on the build's atomics, the forward layout does not.
+// P is stored in the forward layout, which the configuration fixes: the
+// order inside a reverse row is a property of the build (rows of more than
+// 8192 entries keep the order of its atomics).
 namespace {
 
 constexpr char kCkptMagic[8] = {'D', 'P', 'S', 'N', 'N', 'C', 'K', '1'};

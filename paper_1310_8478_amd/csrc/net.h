@@ -216,8 +216,8 @@ hipError_t launch_steps(LaunchSet& L, const Tuning& tune, Timers& tm, hipStream_
 hipError_t launch_read_rows(Net& n, uint32_t i0, uint32_t i1, uint64_t g_lo, uint64_t g_hi,
                             const float* Pg, uint64_t pg_base, uint32_t* tgt_out,
                             uint8_t* dly_out, float* w_out, float* P_out, float* D_out);
-// P between the reverse order (whose order inside a row depends on the build's
-// atomics) and the forward layout (fixed by the configuration), for the
+// P between the reverse order (a property of the build) and the forward
+// layout (fixed by the configuration), for the
 // source columns [c0, c1): Pg holds their forward blocks back to back
 // ((c1 - c0) * Ncol * M floats).  To the forward layout, inhibitory positions
 // are left as they are unless zero_first clears the range first.
