@@ -136,3 +136,55 @@ def test_large_sampled_steps(dp, orc, large):
         large.step(5)
         large.sync()
         assert large.stats()["events"] - s0 == 5 * large.N * cfg["synapses_per_neuron"]
+
+
+def test_large_consolidation_both_forms(dp):
+    # the first consolidation of the full-size network (Sec. 3, Table 2's
+    # long-term plasticity block), at step 39 with decay 1: the folded
+    # derivative is then the P left behind, so every excitatory weight must
+    # equal clamp(w_init + (bias + P)) with D = 0, and inhibitory synapses
+    # stay at w_inh with P = D = 0 -- on sampled rows on both sides of
+    # position 2^31, for the one-pass forward form and the two-pass form,
+    # which must agree bit for bit
+    cfg = W.large(weight_update_period=40, sd_decay=1.0)
+    M = cfg["synapses_per_neuron"]
+    ncol = cfg["neurons_per_column"]
+    N = cfg["grid_x"] * cfg["grid_y"] * ncol
+    Ne = int(round(cfg["exc_fraction"] * ncol))
+    rng = np.random.default_rng(41)
+    rows = np.concatenate([rng.integers(0, N, size=10), rng.integers((2 ** 31) // M + 1, N, size=10),
+                           [N - 1, ncol * 37 + Ne - 1, ncol * 37 + Ne]]).tolist()
+    got = {}
+    for form in (1, 0):
+        _say(f"large: first consolidation, form {form}")
+        net = dp.Network(cfg)
+        try:
+            net.set_tuning(14, form)
+            net.step(40)
+            net.sync()
+            assert net.stats()["consolidations"] == 1
+            if form == 1:
+                # add excitatory sources that spiked (their synapses carry P)
+                _, ids = net.read_spikes(1, 41)
+                exc = np.unique(ids[(ids % ncol) < Ne])
+                assert len(exc) >= 6
+                rows += exc[:3].tolist() + exc[-3:].tolist()
+            got[form] = {i: net.read_weights(i * M, M) for i in rows}
+        finally:
+            net.close()
+    bias = np.float32(cfg["wu_bias"])
+    wmax = np.float32(cfg["w_max"])
+    w0 = np.float32(cfg["w_exc_init"])
+    moved = 0
+    for i in rows:
+        a = got[1][i]
+        for k in ("w", "P", "D"):
+            np.testing.assert_array_equal(a[k].view(np.uint32), got[0][i][k].view(np.uint32), err_msg=k)
+        assert not a["D"].any()
+        if i % ncol < Ne:
+            want = np.clip(w0 + (bias + a["P"]), np.float32(0.0), wmax).astype(np.float32)
+            np.testing.assert_array_equal(a["w"].view(np.uint32), want.view(np.uint32))
+            moved += int((a["P"] != 0).sum())
+        else:
+            assert (a["w"] == np.float32(cfg["w_inh"])).all() and not a["P"].any()
+    assert moved > 0, "some sampled synapse must carry a derivative"
