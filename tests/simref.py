@@ -6,7 +6,8 @@
   use Python's exact integers and its own rounding; STDP pairs are found by
   scanning the spike matrix.
 * stdp_posthoc(): recomputes P, D and w from a raster and the connectivity
-  alone, with a per-synapse state machine advanced in time order.
+  alone, with a per-synapse state machine advanced in time order
+  (stdp_posthoc_synapses: the same for a chosen set of synapses).
 
 Both follow the paper's definitions (Sec. 2: Izhikevich neuron with two 0.5 ms
 sub-steps, delayed injection at t_i + D, STDP dt = t_post - t_pre - d) and the
@@ -167,41 +168,51 @@ def stdp_posthoc(cfg, N, times, ids, tgt, dly, T):
     Per synapse s = (i -> k, d): arrivals happen at first-effect times a = stamp_i + d
     and are processed in step a - 1; post spikes of k stamped t_k potentiate in
     step t_k.  Within a step the order is LTP, then LTD, then consolidation."""
-    Ncol = cfg["neurons_per_column"]
     M = cfg["synapses_per_neuron"]
+    return stdp_posthoc_synapses(cfg, times, ids, np.repeat(np.arange(N), M), tgt, dly, T)
+
+
+def stdp_posthoc_synapses(cfg, times, ids, src, tgt, dly, T):
+    """stdp_posthoc for a chosen set of synapses (source, target, delay
+    arrays): only the spike stamps of the neurons they join are used, so it
+    serves sampled rows of networks too large for the whole arrays."""
+    Ncol = cfg["neurons_per_column"]
     Ne = int(math.floor(float(F(cfg["exc_fraction"])) * Ncol + 0.5))
     tp, tm = tables(cfg)
-    src = np.repeat(np.arange(N), M)
+    src = np.asarray(src, dtype=np.int64)
+    tgt = np.asarray(tgt, dtype=np.int64)
+    dly = np.asarray(dly, dtype=np.int64)
     exc = (src % Ncol) < Ne
-    tgt = tgt.astype(np.int64)
-    dly = dly.astype(np.int64)
+    # the neurons involved, renumbered 0 .. n-1
+    inv, code = np.unique(np.concatenate([src, tgt]), return_inverse=True)
+    csrc, ctgt = code[:len(src)], code[len(src):]
+    nS = len(src)
     w = np.where(exc, F(cfg["w_exc_init"]), F(cfg["w_inh"])).astype(np.float32)
-    P = np.zeros(N * M, dtype=np.float32)
-    D = np.zeros(N * M, dtype=np.float32)
+    P = np.zeros(nS, dtype=np.float32)
+    D = np.zeros(nS, dtype=np.float32)
     NONE = -(1 << 40)
-    last_arr = np.full(N * M, NONE, dtype=np.int64)   # latest arrival time <= now
-    last_post = np.full(N, NONE, dtype=np.int64)      # latest post stamp <= now
-    spk = [[] for _ in range(T + 2)]
-    for s, k in zip(times, ids):
-        spk[int(s)].append(int(k))
-    fired_at = np.zeros((T + 2, N), dtype=bool)
-    for s in range(T + 2):
-        if spk[s]:
-            fired_at[s, spk[s]] = True
+    last_arr = np.full(nS, NONE, dtype=np.int64)          # latest arrival time <= now
+    last_post = np.full(len(inv), NONE, dtype=np.int64)   # latest post stamp <= now
+    times = np.asarray(times, dtype=np.int64)
+    ids = np.asarray(ids, dtype=np.int64)
+    pos = np.searchsorted(inv, ids)
+    keep = (pos < len(inv)) & (inv[np.minimum(pos, len(inv) - 1)] == ids) & (times < T + 2)
+    fired_at = np.zeros((T + 2, len(inv)), dtype=bool)
+    fired_at[times[keep], pos[keep]] = True
     # arrivals per step: synapses whose source fired at stamp t - d + 1
     Tw = cfg["weight_update_period"]
     for t in range(T):
-        if t >= 1 and spk[t]:
-            last_post[spk[t]] = t
-            m = exc & fired_at[t][tgt] & (last_arr != NONE)
+        if t >= 1 and fired_at[t].any():
+            last_post[fired_at[t]] = t
+            m = exc & fired_at[t][ctgt] & (last_arr != NONE)
             # LTP uses arrivals with first effect <= t (registered in earlier steps)
             P[m] = P[m] + tp[t - last_arr[m]]
         s_src = t - dly + 1
         ok = (s_src >= 1)
-        arr = np.zeros(N * M, dtype=bool)
-        arr[ok] = fired_at[s_src[ok], src[ok]]
-        m = arr & exc & (last_post[tgt] != NONE)
-        D[m] = D[m] + tm[t + 1 - last_post[tgt[m]]]
+        arr = np.zeros(nS, dtype=bool)
+        arr[ok] = fired_at[s_src[ok], csrc[ok]]
+        m = arr & exc & (last_post[ctgt] != NONE)
+        D[m] = D[m] + tm[t + 1 - last_post[ctgt[m]]]
         last_arr[arr] = t + 1
         if Tw and (t + 1) % Tw == 0:
             sd = (P - D).astype(np.float32)

@@ -188,3 +188,44 @@ def test_large_consolidation_both_forms(dp):
         else:
             assert (a["w"] == np.float32(cfg["w_inh"])).all() and not a["P"].any()
     assert moved > 0, "some sampled synapse must carry a derivative"
+
+
+def test_large_sampled_stdp_from_raster(dp):
+    # P and D of the full-size network (Sec. 2, the STDP rule and its P / D
+    # split) on sampled rows, recomputed from the network's own raster and
+    # connectivity by the post-hoc checker: 70 steps, rows of excitatory
+    # sources that spiked, random rows and rows beyond position 2^31
+    from simref import stdp_posthoc_synapses
+    cfg = W.large()
+    M = cfg["synapses_per_neuron"]
+    ncol = cfg["neurons_per_column"]
+    N = cfg["grid_x"] * cfg["grid_y"] * ncol
+    Ne = int(round(cfg["exc_fraction"] * ncol))
+    T = 70
+    _say(f"large: {T} steps, sampled P and D against the post-hoc STDP checker")
+    net = dp.Network(cfg)
+    try:
+        net.step(T)
+        net.sync()
+        tt, ii = net.read_spikes(1, T + 1)
+        exc = np.unique(ii[(ii % ncol) < Ne])
+        rng = np.random.default_rng(43)
+        rows = np.unique(np.concatenate([exc[:4], exc[-4:], rng.choice(exc, 4),
+                                         rng.integers(0, N, size=4),
+                                         rng.integers((2 ** 31) // M + 1, N, size=4)])).tolist()
+        got = {i: net.read_weights(i * M, M) for i in rows}
+        conn = {i: net.read_connectivity(i * M, M) for i in rows}
+    finally:
+        net.close()
+    _say(f"  {len(tt)} spikes, {len(rows)} rows")
+    src = np.repeat(np.array(rows, np.int64), M)
+    tgt = np.concatenate([conn[i][0] for i in rows])
+    dly = np.concatenate([conn[i][1] for i in rows])
+    w, P, D = stdp_posthoc_synapses(cfg, tt, ii, src, tgt, dly, T)
+    gP = np.concatenate([got[i]["P"] for i in rows])
+    gD = np.concatenate([got[i]["D"] for i in rows])
+    gw = np.concatenate([got[i]["w"] for i in rows])
+    for name, a, b in (("P", gP, P), ("D", gD, D), ("w", gw, w)):
+        np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32), err_msg=name)
+    _say(f"  {(P != 0).sum()} synapses with P != 0, {(D != 0).sum()} with D != 0")
+    assert (P != 0).sum() >= 20 and (D != 0).sum() >= 20, "the sample must carry derivatives"

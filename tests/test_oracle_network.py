@@ -17,7 +17,7 @@ import pytest
 
 from paper_1310_8478_amd import workloads as W
 
-from simref import brute_force, ensemble_stats, stdp_posthoc, tables, qfix, dqfix
+from simref import brute_force, ensemble_stats, stdp_posthoc, stdp_posthoc_synapses, tables, qfix, dqfix
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -68,6 +68,27 @@ def test_posthoc_stdp_on_tiny_workload(orc, mode):
     np.testing.assert_array_equal(syn["P"].view(np.uint32), P.view(np.uint32))
     np.testing.assert_array_equal(syn["D"].view(np.uint32), D.view(np.uint32))
     np.testing.assert_array_equal(syn["w"].view(np.uint32), w.view(np.uint32))
+
+
+def test_posthoc_stdp_on_chosen_synapses(orc):
+    # the sampled form used at full size: chosen rows (and a scatter of single
+    # synapses) of the tiny workload, against the oracle's arrays
+    cfg = W.tiny(weight_update_period=150)
+    T = 400
+    M = cfg["synapses_per_neuron"]
+    net = orc.Net(cfg, T)
+    net.run(T)
+    tt, ii = net.raster()
+    syn = net.synapses()
+    net.close()
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([ii[:5], rng.integers(0, 5000, size=7)]))
+    sel = np.concatenate([np.arange(i * M, (i + 1) * M) for i in rows.tolist()] +
+                         [rng.integers(0, 5000 * M, size=300)])
+    w, P, D = stdp_posthoc_synapses(cfg, tt, ii, sel // M, syn["tgt"][sel], syn["dly"][sel], T)
+    assert (P != 0).any() and (D != 0).any()
+    for name, a, b in (("w", w, syn["w"][sel]), ("P", P, syn["P"][sel]), ("D", D, syn["D"][sel])):
+        np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32), err_msg=name)
 
 
 def test_delivered_events_and_thalamic_invariants(orc):
