@@ -540,14 +540,6 @@ def bench_paper(args, mode):
         "roofline": None,
         "cpu_baseline": None,
     }
-    return out
-
-
-def bench_serving(args, mode):
-    from paper_1310_8478_amd import workloads as W
-    reqs = W.serving_stream(args.requests, lam=args.rate)
-    out = run_serving(reqs, args.budget_gb, args.quantum, args.warmup_jobs, mode, args.mode,
-                      jobs_out=args.jobs_out)
     print(json.dumps(out))
 
 

@@ -71,7 +71,7 @@ def paper_shaped(grid=(4, 4), M=200, **over) -> dict:
 # The paper's scaling configurations (Table 1): grids of 1000-neuron columns,
 # M = 200, 76/12/8/4 % projection; each measured over 2 s of activity after
 # 8 s of evolution (Sec. 3).  The last grid (6.6 G synapses) needs about
-# 140 GB of device memory.
+# 166 GB of device memory.
 PAPER_TABLE1 = [  # (grid_x, grid_y, paper mean rate Hz, paper wall s per sim s, paper normalized s)
     (1, 1, 27, 0.15, 2.73e-8), (2, 2, 24, 0.4, 5.36e-9), (4, 4, 26, 1.80, 2.41e-8),
     (8, 8, 23, 3.05, 4.22e-9), (16, 16, 22, 6.85, 6.0e-9), (32, 32, 23, 20.0, 4.22e-9),
