@@ -26,9 +26,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per unit of work: the survey's roofline table (state
-# that stays cache-resident -- spike history, currents, offsets, tables -- is
-# not counted).  The device layout stores less than this (a 2-byte target
+# Algorithmic HBM bytes per unit of work, for a plain layout with a 4-byte
+# target index, a weight per synapse and a separate delay byte (state that
+# stays cache-resident -- spike history, currents, offsets, tables -- is not
+# counted).  The device layout stores less than this (a 2-byte target
 # window index, no weight for inhibitory synapses, a packed 4-byte
 # source/delay entry: 14 / 2 / 12 bytes), so these figures are an upper
 # bound of what the kernels must move.
@@ -594,7 +595,7 @@ def evolve(net, target, label, fuse_after=0xFFFFFFFF):
 
 def window_report(cfg, d, wall, steps, first, workload=None, mode=None, measured=False):
     """Throughput, rate and the roofline of the dominant kernel of one timed
-    window (algorithmic bytes of the survey's table over the window's counted
+    window (the algorithmic bytes per unit above times the window's counted
     work units, divided by the kernel's HIP-event time)."""
     N = cfg["grid_x"] * cfg["grid_y"] * cfg["neurons_per_column"]
     M = cfg["synapses_per_neuron"]
