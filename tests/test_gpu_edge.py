@@ -53,6 +53,13 @@ EDGE = {
     "ragged_words": (W.make_config(grid_x=2, grid_y=1, neurons_per_column=65,
                                    synapses_per_neuron=20, thalamic_rate=2.0, w_exc_init=12.0,
                                    weight_update_period=45), 200),
+    # 13 x Ncol x M above 2^28: the network keeps no forward-to-reverse map
+    # and consolidates in the two-pass form; its reverse rows (about 6400
+    # entries) go through the long-row sort
+    "no_consolidation_map": (W.make_config(grid_x=1, grid_y=1, neurons_per_column=2600,
+                                           synapses_per_neuron=8000, w_exc_init=0.05, w_inh=-0.05,
+                                           w_max=1.0, thalamic_rate=30.0, thalamic_current=40.0,
+                                           weight_update_period=40), 100),
     "widest_column": (W.make_config(grid_x=1, grid_y=1, neurons_per_column=65535,
                                     synapses_per_neuron=3, thalamic_rate=300.0, w_exc_init=10.0,
                                     weight_update_period=40), 120),
