@@ -3,7 +3,8 @@
 * Table 1's two smallest grids of 1000-neuron columns, M = 200, the paper's
   76/12/8/4 % projection and the paper-shaped thalamic drive, bit-exact
   against the oracle over 1100 steps (across the first consolidation) in
-  both reproducible summation modes;
+  both reproducible summation modes, and in the unordered mode up to the
+  first consolidation (integer weights: every order gives the same sums);
 * the single-column observable of Fig. 2-3: 320 ms of raster and the
   membrane potential of two excitatory neurons (and one inhibitory), traced
   on the device after a warm-up, bit-exact against the oracle step by step;
@@ -77,6 +78,35 @@ def test_table1_shapes_bitexact(dp, orc, k, mode):
     # the consolidation moved the excitatory weights
     exc = (np.repeat(np.arange(N), 200) % 1000) < 800
     assert (syn["w"][exc] != np.float32(cfg["w_exc_init"])).any()
+
+
+def test_table1_atomic_mode_exact_before_consolidation(dp, orc):
+    # until the first consolidation every weight is 6 or -5 and the thalamic
+    # input 20 mV, so the unordered summation reproduces the oracle bit for
+    # bit on Table 1's 2x2 grid (999 steps, the paper's projection and drive)
+    T = 999
+    cfg = W.paper_table1(1, raster_steps=T + 1)
+    _say(f"Table 1 2x2 grid, atomic mode, {T} steps")
+    net = dp.Network(dict(cfg, sum_mode=W.SUM_ATOMIC))
+    try:
+        net.step(T)
+        net.sync()
+        tt, ii = net.read_spikes(1, T + 1)
+        syn = net.read_weights()
+        v, u = net.read_state()
+    finally:
+        net.close()
+    o = orc.Net(dict(cfg, sum_mode=W.SUM_ORDERED), T)
+    o.run(T)
+    ot, oi = o.raster()
+    os_ = o.synapses()
+    ov, ou = o.state()
+    o.close()
+    assert len(ot) > 10000
+    np.testing.assert_array_equal(tt, ot)
+    np.testing.assert_array_equal(ii, oi)
+    for name, a, b in (("P", syn["P"], os_["P"]), ("D", syn["D"], os_["D"]), ("v", v, ov), ("u", u, ou)):
+        np.testing.assert_array_equal(bits(a), bits(b), err_msg=name)
 
 
 def test_fig23_single_column_trace_bitexact(dp, orc):
