@@ -4,16 +4,21 @@
 //
 //   k_ltp      item 2.1: every neuron stamped t potentiates its incoming
 //              excitatory synapses; workgroups per target column walk the
-//              reverse rows of the column's spiking neurons (contiguous runs).
+//              reverse rows of the column's spiking neurons (contiguous runs);
+//              k_ltp_sp is the wavefront-level form for sparse columns.
 //   k_deliver  items 2.3-2.6: workgroups per source column deliver the
 //              spikes stamped t-d+1 through the column's delay-d synapses,
 //              accumulate the currents of the reachable target columns in an
-//              LDS window, apply LTD, then flush the window.
+//              LDS window, apply LTD, then flush the window (k_deliver_seq:
+//              the ordered-summation form).  k_ltp_deliver runs LTP and
+//              delivery as one launch, which is the default.
 //   k_neuron   item 2.7 plus the thalamic input: Izhikevich update with two
 //              0.5 ms sub-steps, threshold and reset, spike history, and the
 //              raster word of each wavefront written with one ballot.
-//   k_wupdate, k_wupdate_fwd  every weight_update_period steps: fold P - D
-//              into the weights.
+//   k_consolidate  every weight_update_period steps: fold P - D into the
+//              weights in one forward-order pass (k_wupdate + k_wupdate_fwd:
+//              the two-pass form, for networks without the
+//              forward-to-reverse map).
 // Every kernel reads its network's step as t = t0 + tstep: t0 from the
 // network's descriptor, tstep a launch argument.  k_rebase moves t0 forward,
 // which lets one captured graph of G steps be replayed at any step.
